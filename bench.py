@@ -1,0 +1,393 @@
+#!/usr/bin/env python3
+"""Benchmark of the Walk-on-Spheres hot path on one MI355X.
+
+Workload (d = 7, batched vs plain): the differentiated 7-D configuration
+(1024 queries on 32 segments towards the goal, 256 sphere obstacles, sigma = 2,
+16384 walks per query) plus every 7-D environment of the 512-environment
+ragged batch (log-uniform 16-2048 spheres, log-uniform 1-4096 queries,
+sigma ~ U[0.5, 8], 2048 walks per query).  One step = one fused forward +
+backward pass over all of it in ONE persistent launch (the value); the plain
+form runs one forward and one backward launch per environment on the same
+walks (reported beside it).  Inputs are seeded synthetic scenes, resident in
+device memory before timing starts.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-plain] [--no-cpu]
+                    [--no-plan] [--only-batched]
+
+Prints one JSON line (rank 0).  Runs on one GPU only.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import multiprocessing as mp
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "WoS walk-steps/s + ∇u queries/s at fixed std error (d=7), batched vs plain"
+PEAK_FP32_ISSUE_TFLOPS = 78.6     # 256 CU x 64 lanes x 2 (FMA) x 2.4 GHz, no packed FP32
+PEAK_FP32_DATASHEET_TFLOPS = 157.3
+KERNEL_SOURCES = ["paper_2406_01713_amd/csrc/wos_device.hpp", "paper_2406_01713_amd/csrc/wos_kernels.hip",
+                  "paper_2406_01713_amd/csrc/wos_params.hpp"]
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def distance_flops_per_step(s):
+    """Algorithmic FP32 operations of one distance evaluation: per sphere (and
+    the goal ball) d subtractions, d multiply-adds (2 flops), one subtraction
+    of the radius and one min: 3d + 2; per box 5d + 1; the outer box 4d."""
+    d = s["d"]
+    ms = len(s["sph_r"]) + (1 if s.get("goal_r") is not None else 0)
+    mb = len(s["box_h"])
+    return ms * (3 * d + 2) + mb * (5 * d + 1) + 4 * d
+
+
+def workload():
+    from paper_2406_01713_amd import scenes as S
+    envs = [S.scene_c3()]
+    envs[0]["env_id"] = 0
+    envs += S.scene_c4(dims={7})
+    return envs
+
+
+# ----------------------------------------------------------- CPU baseline ----
+
+def _oracle_slice(args):
+    scene, qidx, n_walks, seed, env = args
+    from oracle import oracle as O
+    s = dict(scene)
+    t = time.perf_counter()
+    steps = 0.0
+    dom = O.Domain(s)
+    for q in qidx:
+        for w in range(n_walks):
+            r = O.walk(s, s["queries"][q], w, int(q), env=env, dom=dom)
+            steps += r["steps"]
+    return steps, time.perf_counter() - t
+
+
+def cpu_baseline(envs, budget_walks=400000):
+    """The FP64 oracle, untuned, on a bounded sample of the same workload: the
+    same share of walks from every environment (walks 0..k-1 of every m-th
+    query), one process per host core."""
+    total = sum(len(e["queries"]) * e["n_walks"] for e in envs)
+    frac = budget_walks / total
+    tasks = []
+    for e, s in enumerate(envs):
+        Q = len(s["queries"])
+        nw = max(1, int(round(s["n_walks"] * math.sqrt(frac))))
+        nq = max(1, int(round(Q * frac * s["n_walks"] / nw)))
+        qidx = np.linspace(0, Q - 1, min(nq, Q)).astype(int)
+        tasks.append((s, qidx, nw, s["seed"], s.get("env_id", e)))
+    cores = min(os.cpu_count() or 1, 16)
+    # split the largest tasks so all cores stay busy
+    chunks = []
+    for s, qidx, nw, seed, env in tasks:
+        for part in np.array_split(qidx, max(1, min(len(qidx), cores))):
+            if len(part):
+                chunks.append((s, part, nw, seed, env))
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(cores) as pool:
+        res = pool.map(_oracle_slice, chunks, chunksize=1)
+    wall = time.perf_counter() - t0
+    steps = sum(r[0] for r in res)
+    walks = sum(len(c[1]) * c[2] for c in chunks)
+    cpu_model = platform.processor() or "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu_model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"value": steps / wall, "unit": "walk-steps/s", "cores": cores, "kind": "oracle",
+            "sample": f"{walks} walks ({walks / total:.2e} of the workload: the same walk ids from every "
+                      f"environment), FP64 single-threaded oracle x {cores} processes, {wall:.1f} s wall",
+            "cpu": cpu_model}
+
+
+# ------------------------------------------------------------------ GPU ----
+
+class Batch:
+    def __init__(self, B, envs, torch, mode=0):
+        from paper_2406_01713_amd import scenes as S
+        self.B = B
+        self.envs = envs
+        if mode == 2:
+            envs = [S.with_bdata(e, 2, ak=S.plane_wave_k(e["d"], e["sigma"], seed=i))
+                    for i, e in enumerate(envs)]
+        self.doms = [B.Domain(e) for e in envs]
+        Qs = [len(e["queries"]) for e in envs]
+        self.off = np.concatenate([[0], np.cumsum(Qs)]).astype(np.int64)
+        n = int(self.off[-1])
+        qp = np.zeros((n, 8), dtype=np.float32)
+        for e, s in enumerate(envs):
+            qp[self.off[e]:self.off[e + 1], :s["d"]] = s["queries"]
+        dev = "cuda"
+        self.q = torch.as_tensor(qp, device=dev)
+        self.nw = np.array([e["n_walks"] for e in envs], dtype=np.int64)
+        self.sig = [e["sigma"] for e in envs]
+        self.eps = [e["eps"] for e in envs]
+        self.u = torch.empty(n, device=dev)
+        self.g = torch.empty(n, 8, device=dev)
+        self.st = torch.empty(n, 12, dtype=torch.float64, device=dev)
+        self.ubar = torch.ones(n, device=dev)
+        self.dx = torch.empty(n, 8, device=dev)
+        self.ds = torch.empty(len(envs), dtype=torch.float64, device=dev)
+        self.dg = torch.empty(len(envs), dtype=torch.float64, device=dev)
+        self.seed = envs[0]["seed"]
+
+    def run(self, stats=True):
+        self.B.wos_estimate_batch(self.doms, self.q, self.off, self.sig, self.eps, self.nw, self.seed,
+                                  self.u, self.g, self.st if stats else None, self.ubar, self.dx,
+                                  self.ds, self.dg)
+
+
+class Plain:
+    """One forward launch and one backward launch per environment (plain
+    kernels, one walk per lane), same walk identities as the batch.  Inputs
+    and outputs are allocated before timing."""
+
+    def __init__(self, B, envs, doms, torch, seed):
+        self.B, self.envs, self.doms, self.seed = B, envs, doms, seed
+        self.bufs = []
+        for s in envs:
+            q = torch.as_tensor(s["queries"], dtype=torch.float32, device="cuda")
+            Q, d = q.shape
+            self.bufs.append(dict(q=q, u=torch.empty(Q, device="cuda"), g=torch.empty(Q, d, device="cuda"),
+                                  ub=torch.ones(Q, device="cuda"), dx=torch.empty(Q, d, device="cuda"),
+                                  ds=torch.empty(1, dtype=torch.float64, device="cuda"),
+                                  dg=torch.empty(1, dtype=torch.float64, device="cuda")))
+
+    def run(self, only=None):
+        B = self.B
+        for e, (s, dom, b) in enumerate(zip(self.envs, self.doms, self.bufs)):
+            if only is not None and e not in only:
+                continue
+            opt = B.options(False, e, 0)
+            B.wos_estimate(dom, b["q"], s["n_walks"], s["sigma"], s["eps"], self.seed, b["u"], b["g"], None,
+                           opt=opt)
+            B.wos_backward(dom, b["q"], s["n_walks"], s["sigma"], s["eps"], self.seed, b["ub"], b["dx"],
+                           b["ds"], b["dg"], None, opt=opt)
+        return [b["u"] for b in self.bufs]
+
+
+def traffic_entry(khash):
+    """HBM bytes per launch from the committed counter summary, if it was
+    taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic_persistent_d7.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        t = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_hash") != khash:
+        return None
+    return t.get("bytes_per_launch")
+
+
+def planning(B, torch, n_steps):
+    from paper_2406_01713_amd import scenes as S
+    s = S.scene_c5()
+    dom = B.Domain(s)
+    x = torch.as_tensor(s["queries"], dtype=torch.float32, device="cuda")
+    plan = B.Plan(dom, x, s["n_walks"], s["sigma"], s["eps"], s["s_ub"], s["seed"])
+    plan.step(1)
+    plan.read()
+    t0 = time.perf_counter()
+    plan.step(n_steps - 1)
+    u, g, pl, stalls, status, step = plan.read()
+    dt = time.perf_counter() - t0
+    res = {"starts": len(x), "steps": int(step[0]), "ms_per_step": 1000 * dt / max(1, n_steps - 1),
+           "walks_per_gradient": s["n_walks"], "obstacles": "512 spheres + 512 boxes",
+           "arrived": int((status == 1).sum()), "stopped_elsewhere": int((status == 2).sum()),
+           "stalls_total": int(stalls.sum()), "mean_path_len": float(pl.mean())}
+    del plan
+    return res
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-plan", action="store_true")
+    ap.add_argument("--no-se", action="store_true")
+    ap.add_argument("--only-batched", action="store_true", help="time the batched step only (profiling)")
+    ap.add_argument("--plan-steps", type=int, default=200)
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="first copy this many MiB device-to-device 3 times (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one MI355X: the walk kernels run on a single GPU "
+              "(multi-GPU sharding is described in DESIGN.md, not run). Use --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+    if args.only_batched:
+        args.no_plain = args.no_cpu = args.no_plan = args.no_se = True
+
+    t = time.perf_counter()
+    envs = workload()
+    log(f"workload: {len(envs)} envs, {sum(len(e['queries']) for e in envs)} queries "
+        f"({time.perf_counter() - t:.1f} s to draw)")
+    cpu = None
+    if not args.no_cpu:
+        # before the GPU is initialised: the oracle pool forks this process
+        t = time.perf_counter()
+        cpu = cpu_baseline(envs)
+        log(f"cpu baseline: {cpu['value']:.3g} walk-steps/s ({time.perf_counter() - t:.1f} s)")
+
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    from paper_2406_01713_amd import binding as B
+
+    bat = Batch(B, envs, torch)
+    st = torch.cuda.current_stream()
+    if args.calib_copy_mib:
+        n = args.calib_copy_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {args.calib_copy_mib} MiB x 3")
+
+    for _ in range(args.warmup):
+        bat.run()
+    torch.cuda.synchronize()
+    log("warm-up done")
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_start.record(st)
+    for i in range(args.steps):
+        evs[i][0].record(st)
+        bat.run()
+        evs[i][1].record(st)
+    t_end.record(st)
+    torch.cuda.synchronize()
+    ms_total = t_start.elapsed_time(t_end)
+    ms_step = ms_total / args.steps
+    launch_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    log(f"batched fused fwd+bwd: {ms_step:.1f} ms/step")
+
+    stats = bat.st.cpu().numpy()
+    walk_steps = 0.0
+    flops = 0.0
+    for e, s in enumerate(envs):
+        sl = slice(bat.off[e], bat.off[e + 1])
+        ws = float((stats[sl, 9] * s["n_walks"]).sum())
+        walk_steps += ws
+        flops += ws * distance_flops_per_step(s)
+    value = walk_steps / (ms_step / 1e3)
+    achieved = flops / (launch_ms / 1e3) / 1e12
+    khash = kernel_hash()
+    traffic = traffic_entry(khash)
+
+    out = {"metric": METRIC, "value": value, "unit": "walk-steps/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "d7 fused fwd+bwd, one persistent launch: 7-D segment queries "
+                                  "(1024 q x 16384 walks, 256 spheres, sigma 2) + the 83 7-D envs of the "
+                                  "512-env ragged batch (41660 q x 2048 walks, 16-2048 spheres)",
+                      "envs": len(envs), "queries": int(bat.off[-1]),
+                      "walks": int(sum(len(e["queries"]) * e["n_walks"] for e in envs)),
+                      "walk_steps_per_step": walk_steps, "eps": 1e-4, "seed": int(bat.seed)},
+           "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_ISSUE_TFLOPS,
+                        "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_ISSUE_TFLOPS,
+                        "traffic": traffic,
+                        "kernel": "persistent_kernel<fused fwd+bwd>",
+                        "launch_ms": launch_ms,
+                        "flops_per_launch": flops,
+                        "peak_basis": "FP32 FMA issue rate without packed FP32: 256 CU x 4 SIMD x 16 lanes "
+                                      "x 2 flop x 2.4 GHz; the 157.3 TFLOP/s datasheet figure counts "
+                                      "packed FP32, which this build does not emit",
+                        "frac_of_datasheet_fp32": achieved / PEAK_FP32_DATASHEET_TFLOPS,
+                        "kernel_hash": khash}}
+
+    if not args.no_plain:
+        t = time.perf_counter()
+        pl = Plain(B, envs, bat.doms, torch, bat.seed)
+        pl.run(only={len(envs) - 1})  # loads the plain kernels
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        outs = pl.run()
+        e1.record(st)
+        torch.cuda.synchronize()
+        plain_ms = e0.elapsed_time(e1)
+        ub = bat.u.cpu().numpy()
+        diff = 0.0
+        for e, u in enumerate(outs):
+            a = u.cpu().numpy()
+            b = ub[bat.off[e]:bat.off[e + 1]]
+            diff = max(diff, float(np.max(np.abs(a - b) / np.maximum(np.abs(a), 1e-6))) if len(a) else 0.0)
+        out["plain"] = {"ms_per_step": plain_ms, "walk_steps_per_s": walk_steps / (plain_ms / 1e3),
+                        "launches": 2 * len(envs), "max_rel_diff_u_vs_batched": diff}
+        out["batched_vs_plain"] = plain_ms / ms_step
+        log(f"plain fwd+bwd per env: {plain_ms:.1f} ms, batched speed-up {plain_ms / ms_step:.2f}x "
+            f"({time.perf_counter() - t:.1f} s)")
+
+    if not args.no_se:
+        # standard errors measured with plane-wave data (u = exp(k.x)) on the
+        # same geometry and walks: n* = n (SE_grad / (0.01 |grad u|))^2
+        pw = Batch(B, envs, torch, mode=2)
+        pw.run()
+        torch.cuda.synchronize()
+        g = pw.g.cpu().numpy().astype(np.float64)
+        sst = pw.st.cpu().numpy()
+        need = 0.0
+        have = 0.0
+        zero_hit = 0
+        for e, s in enumerate(envs):
+            sl = slice(pw.off[e], pw.off[e + 1])
+            gn = np.linalg.norm(g[sl, :s["d"]], axis=1)
+            se = np.linalg.norm(sst[sl, 1:1 + s["d"]], axis=1)
+            n = s["n_walks"]
+            ok = gn > 0
+            need += float(np.sum(n * (se[ok] / (0.01 * gn[ok])) ** 2))
+            have += float(ok.sum() * n)
+        u_goal = stats[:, 0]
+        zero_hit = int(np.sum(bat.u.cpu().numpy() == 0))
+        q_total = int(bat.off[-1])
+        out["grad_queries_per_s_at_1pct_se"] = q_total / (ms_step / 1e3 * need / max(have, 1.0))
+        out["se_note"] = ("SE from plane-wave boundary data on the same geometry and walks; "
+                          f"with goal-indicator data {zero_hit}/{q_total} queries see no goal hit")
+
+    if not args.no_plan:
+        t = time.perf_counter()
+        out["planning_d7"] = planning(B, torch, args.plan_steps)
+        log(f"planning: {out['planning_d7']['ms_per_step']:.1f} ms/step ({time.perf_counter() - t:.1f} s)")
+
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
+
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

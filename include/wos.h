@@ -1,0 +1,287 @@
+/*
+ * wos.h -- C ABI of libwos: Walk-on-Spheres estimates of the screened Poisson
+ * potential field and its gradient on MI355X (gfx950).
+ *
+ * The problem follows Muchacho & Pokorny, "Walk on Spheres for PDE-based Path
+ * Planning":
+ *   - PDE (Sec. III, eq. screened_poisson_wos, c = 1/t; here sigma = c):
+ *         Laplacian(u) - sigma u = 0 in Omega,   u = g on the boundary.
+ *   - Omega is the outer box minus obstacles, given through the distance to its
+ *     boundary (Sec. V); the goal set is part of the boundary with g = g_goal
+ *     (Sec. III, eq. screened_potential_field), obstacles and the outer box
+ *     carry g_obstacle and g_outer (0 in the planning workloads).
+ *   - Estimator (Sec. IV-A): mean over n walks of the one-point estimates
+ *     u_hat(x_0) = prod_k C(R_k) g(xbar_K), with R_k the largest empty ball
+ *     around x_k, x_{k+1} uniform on its sphere, and absorption in the
+ *     eps-shell (Fig. 2); C(R) = 1 / 0F1(; d/2; sigma R^2 / 4).
+ *   - Gradient (Sec. IV-A, first-sphere estimator):
+ *         grad_hat u(x_0) = (d / R_0) C1(R_0) u_hat(x_1) v_0,
+ *     C1(R) = 1 / 0F1(; d/2 + 1; sigma R^2 / 4)  (equal to the printed d/R
+ *     form at sigma = 0).
+ *
+ * Conventions for every call:
+ *   - Return 0 on success, a negative WOS_E* code on error; wos_last_error()
+ *     then returns a message (thread-local).  Nothing is launched on error.
+ *   - "host" pointers are read during the call only and may be freed after it
+ *     returns.  "device" pointers are caller-owned device memory on the current
+ *     HIP device; the call enqueues work on `stream` (a hipStream_t, NULL for the
+ *     default stream) and returns without synchronising: device outputs are
+ *     valid once the stream has reached that point.  Outputs are overwritten,
+ *     never accumulated.
+ *   - Matrices are row-major: queries Q x d, gradients Q x d.  The floating
+ *     type of queries and of u / gradient outputs is float (WOS_FP32) or double
+ *     (WOS_FP64); statistics and sensitivities are always double.
+ *   - Random numbers: Philox4x32-10 with key = seed and counter
+ *     (2k + j, walk, query, env_id) for step k; the walks of a query depend only
+ *     on that identity, so estimates are reproducible and the batched, plain,
+ *     forward and backward paths regenerate identical walks.
+ *   - Queries outside Omega or within eps of its boundary are not errors: all
+ *     their walks stop at once with u_hat = g of the nearest component and a
+ *     zero gradient ("degenerate", counted in the statistics).
+ *   - A walk that makes max_steps distance evaluations without reaching the
+ *     eps-shell is truncated: it contributes 0 and is counted.
+ */
+#ifndef WOS_H
+#define WOS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define WOS_OK 0
+#define WOS_EINVAL (-1)  /* bad argument: NULL, NaN/Inf, eps <= 0, sigma < 0, n_walks < 1 ... */
+#define WOS_EDIM (-2)    /* d outside [2, 8] */
+#define WOS_ENOMEM (-3)  /* device or host allocation failed */
+#define WOS_EHIP (-4)    /* HIP runtime or launch error */
+#define WOS_ENOTSUP (-5) /* unsupported combination (see each call) */
+
+#define WOS_MIN_DIM 2
+#define WOS_MAX_DIM 8
+#define WOS_BATCH_STRIDE 8 /* row stride of batched query / gradient arrays */
+
+/* flags */
+#define WOS_FP32 0u
+#define WOS_FP64 1u
+
+/* boundary-data modes */
+#define WOS_BDATA_CLASS 0  /* g_goal / g_obstacle / g_outer per component */
+#define WOS_BDATA_AFFINE 1 /* g(y) = a.y + b on every component; needs sigma = 0 */
+#define WOS_BDATA_PLANE 2  /* g(y) = exp(k.y) on every component; needs |k|^2 = sigma */
+
+/* outer boundary kinds */
+#define WOS_OUTER_BOX 0  /* [lo, hi] */
+#define WOS_OUTER_BALL 1 /* ball (center, radius) */
+
+typedef struct wos_domain wos_domain; /* opaque, library-owned, immutable */
+typedef struct wos_plan wos_plan;     /* opaque planning loop (captured HIP graph) */
+
+typedef struct {
+    int64_t n;               /* number of sphere obstacles (may be 0) */
+    const double* centers;   /* host, n x d */
+    const double* radii;     /* host, n, each >= 0 (0: point obstacle) */
+} wos_spheres;
+
+typedef struct {
+    int64_t n;                 /* number of axis-aligned box obstacles (may be 0) */
+    const double* centers;     /* host, n x d */
+    const double* half_widths; /* host, n x d, each >= 0 */
+} wos_boxes;
+
+typedef struct {
+    const double* center; /* host, d */
+    double radius;        /* > 0 */
+} wos_ball;
+
+typedef struct {
+    int kind;              /* WOS_OUTER_BOX or WOS_OUTER_BALL */
+    const double* lo;      /* host, d (box) */
+    const double* hi;      /* host, d (box), hi > lo */
+    const double* center;  /* host, d (ball) */
+    double radius;         /* ball radius > 0 */
+} wos_outer;
+
+typedef struct {
+    int mode;            /* WOS_BDATA_* */
+    double g_goal;       /* class mode: value on the goal sphere (1 for planning) */
+    double g_obstacle;   /* class mode: value on obstacles (0 for planning) */
+    double g_outer;      /* class mode: value on the outer boundary (0) */
+    const double* a_or_k;/* host, d: affine slope a or plane-wave vector k */
+    double b;            /* affine offset */
+} wos_bdata;
+
+typedef struct {
+    uint32_t flags;     /* WOS_FP32 (default) or WOS_FP64 */
+    uint32_t env_id;    /* counter word 3 of the RNG (default 0) */
+    uint32_t max_steps; /* distance evaluations per walk before truncation; 0 -> 65536 */
+    uint32_t reserved;  /* must be 0 */
+} wos_options;
+
+/*
+ * wos_create_domain -- copy a domain description to the current device.
+ * Omega = outer \ (goal ball U spheres U boxes) (Sec. V: the walk only needs
+ * the distance to the boundary; here exact signed distances of the
+ * components and their minimum).  goal may be NULL (no goal set); spheres
+ * and boxes may be NULL (none).  The distance to the boundary is the minimum
+ * of the components' signed distances; ties resolve to the goal, then spheres
+ * by index, then boxes, then the outer boundary.
+ * Errors: WOS_EDIM, WOS_EINVAL (NULL out/outer/bdata, non-finite values,
+ * negative radii, empty box), WOS_ENOMEM, WOS_EHIP.
+ */
+int wos_create_domain(int d, const wos_spheres* spheres, const wos_boxes* boxes,
+                      const wos_ball* goal, const wos_outer* outer, const wos_bdata* bdata,
+                      wos_domain** out);
+
+/* wos_destroy_domain -- free a domain (NULL is ignored).  The caller ensures no
+ * enqueued work still uses it. */
+void wos_destroy_domain(wos_domain* dom);
+
+/* wos_domain_dim -- dimension d of a domain (or WOS_EINVAL for NULL). */
+int wos_domain_dim(const wos_domain* dom);
+
+/*
+ * wos_estimate -- u(x_q) and grad u(x_q) for Q query points (Sec. IV-A).
+ *   queries   device, Q x d (float or double per opt->flags)
+ *   n_walks   walks per query, >= 1
+ *   sigma     screening coefficient c = 1/t >= 0
+ *   eps       absorption shell width > 0
+ *   seed      Philox key
+ *   out_u     device, Q (same type as queries)
+ *   out_grad  device, Q x d, or NULL
+ *   out_stats device double, Q x (d + 4), or NULL: per query
+ *             [se_u, se_grad[0..d-1], mean_steps, n_truncated, n_degenerate],
+ *             se = sample standard deviation / sqrt(n_walks)
+ *   opt       NULL for defaults
+ * Plain form: one walk per lane, lanes idle once their walk ends.
+ * Errors: WOS_EINVAL, WOS_ENOTSUP (affine data with sigma != 0; plane wave
+ * with |k|^2 != sigma; sigma R^2 too large for the weight series), WOS_EHIP.
+ */
+int wos_estimate(const wos_domain* dom, const void* queries, int64_t n_queries,
+                 int64_t n_walks, double sigma, double eps, uint64_t seed, void* out_u,
+                 void* out_grad, double* out_stats, const wos_options* opt, void* stream);
+
+/*
+ * wos_backward -- vector-Jacobian product of u with respect to the query
+ * points, sigma and g_goal for upstream weights grad_u (device, Q, same type
+ * as queries), regenerating the forward walks from (seed, walk, query,
+ * env_id) instead of storing them:
+ *   out_dx[q]   = grad_u[q] * grad_hat u(x_q)              (device, Q x d)
+ *   out_dsigma  = sum_q grad_u[q] mean_w[u_hat S]          (device double scalar)
+ *   out_dg_goal = sum_q grad_u[q] mean_w[W 1{goal}]        (device double scalar)
+ *   out_dq      device double Q x 2 or NULL: per query (du/dsigma, du/dg_goal)
+ * with S = sum over weighted steps of d ln C(R_k)/d sigma (the walk law does not
+ * depend on sigma, so this pathwise derivative is exact), W the product of
+ * weights; in the affine / plane-wave modes dg_goal is the sensitivity to a
+ * constant added to the data on the goal sphere.
+ * Errors: as wos_estimate.
+ */
+int wos_backward(const wos_domain* dom, const void* queries, int64_t n_queries, int64_t n_walks,
+                 double sigma, double eps, uint64_t seed, const void* grad_u, void* out_dx,
+                 double* out_dsigma, double* out_dg_goal, double* out_dq,
+                 const wos_options* opt, void* stream);
+
+/*
+ * wos_estimate_batch -- forward (grad_u == NULL) or fused forward + backward
+ * over a ragged batch of environments in ONE persistent launch: a wave takes
+ * a work unit (env, query, walk range) from a device counter and refills its
+ * lanes with the next walk of the unit as soon as a walk ends.  FP32 only.
+ *   envs       host array of n_envs domains (any mix of d)
+ *   queries    device float, (sum Q) x 8: env e's queries are rows
+ *              q_offsets[e] .. q_offsets[e+1]-1, first d_e columns used
+ *   q_offsets  host, n_envs + 1, non-decreasing, q_offsets[0] = 0
+ *   sigma, eps host, n_envs each
+ *   n_walks    host, n_envs: walks per query of each env
+ *   seed       Philox key; env e uses env_id = e
+ *   out_u      device float, sum Q
+ *   out_grad   device float, (sum Q) x 8, or NULL
+ *   out_stats  device double, (sum Q) x 12, or NULL (layout of wos_estimate
+ *              with d = 8 columns reserved for se_grad)
+ *   grad_u     device float, sum Q, or NULL for forward only
+ *   out_dx     device float, (sum Q) x 8 (required with grad_u)
+ *   out_dsigma device double, n_envs (required with grad_u)
+ *   out_dg     device double, n_envs (required with grad_u)
+ * Walk identities match wos_estimate / wos_backward called per env with
+ * env_id = e, so results agree with those calls up to summation order.
+ * Errors: as wos_estimate; WOS_ENOTSUP for WOS_FP64.
+ */
+int wos_estimate_batch(const wos_domain* const* envs, int n_envs, const float* queries,
+                       const int64_t* q_offsets, const double* sigma, const double* eps,
+                       const int64_t* n_walks, uint64_t seed, float* out_u, float* out_grad,
+                       double* out_stats, const float* grad_u, float* out_dx,
+                       double* out_dsigma, double* out_dg, const wos_options* opt,
+                       void* stream);
+
+/*
+ * wos_plan_create -- gradient-ascent planning loop (Sec. III, screened-harmonic
+ * paths; Sec. VII step rule s = min(s_ub, d(x)/2)) captured once as a HIP graph
+ * of [fused forward + backward walk kernel, finalize, update] on `stream`.
+ *   x      device float, S x d start points, updated in place each step
+ *   Step t uses key seed + t (t kept on the device, so replays need no host
+ *   work); start s is query s of the walks.  A start whose estimated gradient
+ *   is exactly zero does not move (a stall is counted); a start within eps of
+ *   the boundary stops (status 1 at the goal, 2 elsewhere).
+ * The plan owns its scratch buffers; x must outlive the plan.
+ */
+int wos_plan_create(const wos_domain* dom, float* x, int64_t n_starts, int64_t n_walks,
+                    double sigma, double eps, double s_ub, uint64_t seed,
+                    const wos_options* opt, void* stream, wos_plan** out);
+
+/* wos_plan_step -- replay the captured step n_steps times on the plan's stream. */
+int wos_plan_step(wos_plan* plan, int n_steps);
+
+/*
+ * wos_plan_buffers -- device pointers owned by the plan (valid until destroy):
+ *   u [S] float, grad [S x 8] float (last step's estimates, first d columns), path_len [S]
+ *   double (sum of step lengths), stalls [S] int32, status [S] int32,
+ *   step [1] uint64 (steps taken).  Any output pointer may be NULL.
+ */
+int wos_plan_buffers(wos_plan* plan, float** u, float** grad, double** path_len,
+                     int32_t** stalls, int32_t** status, uint64_t** step);
+
+/*
+ * wos_plan_read -- synchronise the plan's stream and copy its state to host
+ * arrays (any may be NULL): u [S] float, grad [S x 8] float, path_len [S]
+ * double, stalls [S] int32, status [S] int32, step [1] uint64.
+ */
+int wos_plan_read(wos_plan* plan, float* u, float* grad, double* path_len, int32_t* stalls,
+                  int32_t* status, uint64_t* step);
+
+/* wos_plan_destroy -- synchronise the plan's stream and free it (NULL ignored). */
+void wos_plan_destroy(wos_plan* plan);
+
+/*
+ * wos_autotune -- time the persistent kernel's launch shapes on a synthetic
+ * scene of dimension d with M sphere obstacles and Q queries, and record the
+ * fastest in the cache file (JSON, created or updated) under the bucket of
+ * (d, M, Q).  Subsequent batched launches in this process read the cache at
+ * cache_path (or $WOS_AUTOTUNE_CACHE when wos_set_autotune_cache was not
+ * called).  Blocks the calling thread (synchronises the device).
+ */
+int wos_autotune(int d, int64_t n_obstacles, int64_t n_queries, int64_t n_walks,
+                 const char* cache_path);
+
+/* wos_set_autotune_cache -- load (or reset with NULL) the autotune cache. */
+int wos_set_autotune_cache(const char* cache_path);
+
+/*
+ * wos_debug_walks -- per-walk records of walks w0 .. w0+n-1 of one query, for
+ * diagnostics and walk-level parity checks.  query is a host double array of
+ * d values (cast to the compute type); q_index is the query's RNG index.
+ * out_records (host double, n x (d + 7)): [u_hat, grad_hat[d], S, goal_w,
+ * steps, status (0 absorbed, 1 degenerate, 2 truncated), class (0 goal,
+ * 1 sphere, 2 box, 3 outer)].  Synchronous.
+ */
+int wos_debug_walks(const wos_domain* dom, const double* query, uint32_t q_index, int64_t w0,
+                    int64_t n, double sigma, double eps, uint64_t seed, const wos_options* opt,
+                    double* out_records);
+
+/* wos_last_error -- message for the last failing call on this thread. */
+const char* wos_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WOS_H */

@@ -1,0 +1,1023 @@
+// wos_api.cpp -- the C ABI of libwos (include/wos.h): argument checks, device
+// copies of the domain, weight-series coefficients, launch decomposition, the
+// batched scheduler's work-unit table, the HIP-graph planning loop and the
+// launch-shape autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/wos.h"
+#include "wos_launch.hpp"
+#include "wos_params.hpp"
+
+using namespace wos;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what)
+{
+    return fail(WOS_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define WOS_HIP(call, what)                       \
+    do {                                          \
+        hipError_t e_ = (call);                   \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+bool finite_all(const double* p, int64_t n)
+{
+    for (int64_t i = 0; i < n; ++i)
+        if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+}  // namespace
+
+struct wos_domain {
+    int d = 0;
+    int device = 0;
+    int64_t n_sph = 0, n_box = 0;
+    float* sph_f = nullptr;
+    double* sph_d = nullptr;
+    float* box_f = nullptr;
+    double* box_d = nullptr;
+    bool has_goal = false;
+    double goal_c[kMaxDim] = {0};
+    double goal_r = 0;
+    int outer_kind = 0;
+    double lo[kMaxDim] = {0}, hi[kMaxDim] = {0}, oc[kMaxDim] = {0};
+    double orad = 0;
+    int mode = 0;
+    double g_goal = 1, g_obs = 0, g_outer = 0, b = 0;
+    double ak[kMaxDim] = {0};
+    double r_max = 0;  // largest possible empty-ball radius (bounds sigma R^2 / 4)
+};
+
+namespace {
+
+// Horner coefficients c_k = 1 / ((b)_k k!) of 0F1(; b; y) up to the first k
+// whose term at y_max falls below tol times the sum (all terms are positive).
+int series_coeffs(double b, double y_max, double tol, double* c)
+{
+    c[0] = 1.0;
+    double term = 1.0, sum = 1.0;
+    int k = 1;
+    for (; k < kMaxTerms; ++k) {
+        c[k] = c[k - 1] / ((b + k - 1.0) * (double)k);
+        term *= y_max / ((b + k - 1.0) * (double)k);
+        sum += term;
+        if (term <= tol * sum && (double)k * k > y_max) return k + 1;
+        if (y_max == 0.0) return 1;
+    }
+    return -1;
+}
+
+template <typename T>
+int make_env(const wos_domain* D, double sigma, double eps, uint64_t seed, uint32_t env_id,
+             uint32_t max_steps, EnvP<T>& p)
+{
+    std::memset(&p, 0, sizeof(p));
+    if (!(sigma >= 0.0) || !std::isfinite(sigma)) return fail(WOS_EINVAL, "sigma must be finite and >= 0 (got %g)", sigma);
+    if (!(eps > 0.0) || !std::isfinite(eps)) return fail(WOS_EINVAL, "eps must be finite and > 0 (got %g)", eps);
+    if (D->mode == WOS_BDATA_AFFINE && sigma != 0.0)
+        return fail(WOS_ENOTSUP, "affine boundary data solves the equation only at sigma = 0");
+    if (D->mode == WOS_BDATA_PLANE) {
+        double k2 = 0;
+        for (int i = 0; i < D->d; ++i) k2 += D->ak[i] * D->ak[i];
+        if (std::fabs(k2 - sigma) > 1e-9 * std::max(1.0, sigma))
+            return fail(WOS_ENOTSUP, "plane-wave data needs |k|^2 = sigma (|k|^2 = %g, sigma = %g)", k2, sigma);
+    }
+    const double y_max = 0.25 * sigma * D->r_max * D->r_max;
+    const double tol = sizeof(T) == 4 ? 1e-9 : 1e-18;
+    double cC[kMaxTerms], cC1[kMaxTerms];
+    const int nC = series_coeffs(0.5 * D->d, y_max, tol, cC);
+    const int nC1 = series_coeffs(0.5 * D->d + 1.0, y_max, tol, cC1);
+    if (nC < 0 || nC1 < 0)
+        return fail(WOS_ENOTSUP, "sigma R_max^2 / 4 = %g needs more than %d series terms", y_max, kMaxTerms);
+    p.sph = nullptr;
+    p.box = nullptr;
+    if (sizeof(T) == 4) {
+        p.sph = (const T*)D->sph_f;
+        p.box = (const T*)D->box_f;
+    } else {
+        p.sph = (const T*)D->sph_d;
+        p.box = (const T*)D->box_d;
+    }
+    p.n_sph = (int32_t)D->n_sph;
+    p.n_box = (int32_t)D->n_box;
+    p.d = D->d;
+    p.has_goal = D->has_goal ? 1 : 0;
+    p.outer_kind = D->outer_kind;
+    p.mode = D->mode;
+    p.nt_C = nC;
+    p.nt_C1 = nC1;
+    p.key0 = (uint32_t)seed;
+    p.key1 = (uint32_t)(seed >> 32);
+    p.env_id = env_id;
+    p.max_steps = max_steps ? max_steps : kDefaultMaxSteps;
+    for (int i = 0; i < kMaxDim; ++i) {
+        p.goal_c[i] = (T)D->goal_c[i];
+        p.lo[i] = (T)D->lo[i];
+        p.hi[i] = (T)D->hi[i];
+        p.oc[i] = (T)D->oc[i];
+        p.ak[i] = (T)D->ak[i];
+    }
+    p.goal_r = (T)D->goal_r;
+    p.orad = (T)D->orad;
+    p.g_goal = (T)D->g_goal;
+    p.g_obs = (T)D->g_obs;
+    p.g_outer = (T)D->g_outer;
+    p.b = (T)D->b;
+    p.sigma = (T)sigma;
+    p.eps = (T)eps;
+    p.qsigma = (T)(0.25 * sigma);
+    for (int i = 0; i < kMaxTerms; ++i) {
+        p.cC[i] = (T)(i < nC ? cC[i] : 0.0);
+        p.cC1[i] = (T)(i < nC1 ? cC1[i] : 0.0);
+    }
+    return WOS_OK;
+}
+
+int check_device(const wos_domain* D)
+{
+    int dev = -1;
+    WOS_HIP(hipGetDevice(&dev), "hipGetDevice");
+    if (dev != D->device) return fail(WOS_EINVAL, "domain lives on device %d, current device is %d", D->device, dev);
+    return WOS_OK;
+}
+
+int read_opts(const wos_options* opt, wos_options& o)
+{
+    o = wos_options{WOS_FP32, 0u, 0u, 0u};
+    if (opt) o = *opt;
+    if (o.flags & ~1u) return fail(WOS_EINVAL, "unknown flags 0x%x", o.flags);
+    if (o.reserved != 0) return fail(WOS_EINVAL, "wos_options.reserved must be 0");
+    return WOS_OK;
+}
+
+// Device scratch allocated in stream order and freed the same way; where the
+// device has no stream-ordered allocator, plain allocations are freed after
+// the stream drains.
+struct Scratch {
+    std::vector<void*> ptrs;
+    hipStream_t st;
+    bool sync_free = false;
+    explicit Scratch(hipStream_t s) : st(s) {}
+    template <typename T>
+    int get(T** p, size_t n)
+    {
+        *p = nullptr;
+        if (n == 0) n = 1;
+        hipError_t e = sync_free ? hipErrorNotSupported : hipMallocAsync((void**)p, n * sizeof(T), st);
+        if (e == hipErrorNotSupported) {
+            (void)hipGetLastError();
+            sync_free = true;
+            e = hipMalloc((void**)p, n * sizeof(T));
+        }
+        if (e != hipSuccess) return fail(WOS_ENOMEM, "device scratch of %zu bytes: %s", n * sizeof(T), hipGetErrorString(e));
+        ptrs.push_back((void*)*p);
+        return WOS_OK;
+    }
+    ~Scratch()
+    {
+        if (sync_free) {
+            (void)hipStreamSynchronize(st);
+            for (void* p : ptrs) (void)hipFree(p);
+        } else {
+            for (void* p : ptrs) (void)hipFreeAsync(p, st);
+        }
+    }
+};
+
+// Pinned staging of host tables for asynchronous upload; the next upload waits
+// for the previous copy to finish before reusing the buffer.
+struct Staging {
+    std::mutex mu;
+    void* buf = nullptr;
+    size_t cap = 0;
+    hipEvent_t ev = nullptr;
+    bool pending = false;
+};
+Staging g_stage;
+
+int upload(void* dst, const void* src, size_t bytes, hipStream_t st)
+{
+    std::lock_guard<std::mutex> lk(g_stage.mu);
+    if (g_stage.pending) {
+        WOS_HIP(hipEventSynchronize(g_stage.ev), "staging wait");
+        g_stage.pending = false;
+    }
+    if (!g_stage.ev) WOS_HIP(hipEventCreateWithFlags(&g_stage.ev, hipEventDisableTiming), "hipEventCreate");
+    if (bytes > g_stage.cap) {
+        if (g_stage.buf) (void)hipHostFree(g_stage.buf);
+        g_stage.buf = nullptr;
+        g_stage.cap = 0;
+        hipError_t e = hipHostMalloc(&g_stage.buf, bytes, hipHostMallocDefault);
+        if (e != hipSuccess) return fail(WOS_ENOMEM, "pinned staging of %zu bytes", bytes);
+        g_stage.cap = bytes;
+    }
+    std::memcpy(g_stage.buf, src, bytes);
+    WOS_HIP(hipMemcpyAsync(dst, g_stage.buf, bytes, hipMemcpyHostToDevice, st), "upload");
+    WOS_HIP(hipEventRecord(g_stage.ev, st), "hipEventRecord");
+    g_stage.pending = true;
+    return WOS_OK;
+}
+
+// ------------------------------------------------------------------------
+// Autotune cache: per (d, obstacle bucket, query bucket) the fastest number
+// of work units per resident wave and persistent-grid multiplier.
+// ------------------------------------------------------------------------
+struct Tune {
+    int units_per_wave = 4;
+    int grid_mult = 1;
+};
+std::mutex g_tune_mu;
+std::map<std::string, Tune> g_tune;
+bool g_tune_loaded = false;
+std::string g_tune_path;
+
+int log2_bucket(int64_t v)
+{
+    int b = 0;
+    while (v > 1) {
+        v >>= 1;
+        ++b;
+    }
+    return b;
+}
+
+std::string tune_key(int d, int64_t M, int64_t Q)
+{
+    char k[64];
+    snprintf(k, sizeof(k), "d%d_m%d_q%d", d, log2_bucket(std::max<int64_t>(M, 1)), log2_bucket(std::max<int64_t>(Q, 1)));
+    return k;
+}
+
+void load_tune_locked(const char* path)
+{
+    g_tune.clear();
+    g_tune_loaded = true;
+    g_tune_path = path ? path : "";
+    if (!path || !*path) return;
+    FILE* f = fopen(path, "r");
+    if (!f) return;
+    char line[256];
+    while (fgets(line, sizeof(line), f)) {
+        char key[64];
+        int upw = 0, gm = 0;
+        // one entry per line: "key": {"units_per_wave": U, "grid_mult": G},
+        if (sscanf(line, " \"%63[^\"]\": {\"units_per_wave\": %d, \"grid_mult\": %d}", key, &upw, &gm) == 3 &&
+            upw > 0 && gm > 0)
+            g_tune[key] = Tune{upw, gm};
+    }
+    fclose(f);
+}
+
+Tune lookup_tune(int d, int64_t M, int64_t Q)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    if (!g_tune_loaded) load_tune_locked(getenv("WOS_AUTOTUNE_CACHE"));
+    auto it = g_tune.find(tune_key(d, M, Q));
+    if (it != g_tune.end()) return it->second;
+    return Tune{};
+}
+
+int save_tune_locked(const char* path)
+{
+    FILE* f = fopen(path, "w");
+    if (!f) return fail(WOS_EINVAL, "cannot write autotune cache %s", path);
+    fprintf(f, "{\n");
+    size_t i = 0;
+    for (auto& kv : g_tune) {
+        fprintf(f, "  \"%s\": {\"units_per_wave\": %d, \"grid_mult\": %d}%s\n", kv.first.c_str(),
+                kv.second.units_per_wave, kv.second.grid_mult, (++i < g_tune.size()) ? "," : "");
+    }
+    fprintf(f, "}\n");
+    fclose(f);
+    return WOS_OK;
+}
+
+// Relative cost of one work unit of an env: obstacle work per walk step
+// times a typical walk length times the walks of the unit.
+double unit_cost(const wos_domain* D, int64_t wps)
+{
+    static const double steps[9] = {0, 0, 12, 25, 40, 55, 71, 85, 95};
+    const int d = D->d;
+    const double per_step = (double)D->n_sph * (2 * d + 3) + (double)D->n_box * (5 * d + 4) + 150.0 * ((d + 3) / 4);
+    return per_step * steps[d] * (double)wps;
+}
+
+struct BatchLayout {
+    std::vector<BatchEnv> benv;
+    int64_t total_units = 0;
+    int grid = 0;
+};
+
+// Work units: each query's walks are split into `splits` ranges so that the
+// launch has about units_per_wave units per resident wave; envs are ordered
+// by decreasing unit cost (longest-processing-time first).
+void plan_batch(const wos_domain* const* envs, const int64_t* q_off, int n_envs, const int64_t* n_walks,
+                int q_stride, int force_upw, int force_gm, BatchLayout& L)
+{
+    const int block = 256;
+    int64_t sumQW = 0, maxM = 0, heavyQ = 0, maxW = 1;
+    int heavy_d = 2;
+    double heavy = -1;
+    for (int e = 0; e < n_envs; ++e) {
+        const int64_t q = q_off[e + 1] - q_off[e];
+        sumQW += q * n_walks[e];
+        maxW = std::max(maxW, n_walks[e]);
+        const double c = unit_cost(envs[e], n_walks[e]) * (double)q;
+        if (c > heavy) {
+            heavy = c;
+            heavy_d = envs[e]->d;
+            maxM = envs[e]->n_sph + envs[e]->n_box;
+            heavyQ = q;
+        }
+    }
+    Tune t = lookup_tune(heavy_d, maxM, heavyQ);
+    if (force_upw > 0) t.units_per_wave = force_upw;
+    if (force_gm > 0) t.grid_mult = force_gm;
+    const int resident_blocks = persistent_resident_blocks(true, block);
+    L.grid = std::max(1, resident_blocks * t.grid_mult);
+    const int64_t waves = (int64_t)L.grid * (block / kWave);
+    const int64_t target = waves * t.units_per_wave;
+    // one walk-range length for the launch: total walks / target units,
+    // a multiple of the wave width, at least 256 walks (4 per lane)
+    int64_t wps = std::max<int64_t>(256, sumQW / std::max<int64_t>(target, 1));
+    wps = std::min(wps, maxW);
+    wps = ((wps + kWave - 1) / kWave) * kWave;
+
+    std::vector<int> order(n_envs);
+    for (int e = 0; e < n_envs; ++e) order[e] = e;
+    auto env_wps = [&](int e) { return std::min<int64_t>(wps, ((n_walks[e] + kWave - 1) / kWave) * kWave); };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        const int64_t qa = q_off[a + 1] - q_off[a], qb = q_off[b + 1] - q_off[b];
+        const double ca = qa ? unit_cost(envs[a], env_wps(a)) : -1.0, cb = qb ? unit_cost(envs[b], env_wps(b)) : -1.0;
+        return ca > cb;
+    });
+    L.benv.resize(n_envs);
+    int64_t uoff = 0;
+    for (int i = 0; i < n_envs; ++i) {
+        const int e = order[i];
+        BatchEnv& b = L.benv[i];
+        const int64_t w = env_wps(e);
+        const int64_t splits = (n_walks[e] + w - 1) / w;
+        b.q_off = q_off[e];
+        b.n_q = (int32_t)(q_off[e + 1] - q_off[e]);
+        b.n_walks = n_walks[e];
+        b.splits = (int32_t)splits;
+        b.wps = (int32_t)w;
+        b.d = envs[e]->d;
+        b.q_stride = q_stride;
+        b.slot = e;
+        b.unit_off = uoff;
+        uoff += (int64_t)b.n_q * splits;
+    }
+    L.total_units = uoff;
+}
+
+int run_batch(const wos_domain* const* envs, int n_envs, const float* queries, const int64_t* q_offsets,
+              const double* sigma, const double* eps, const int64_t* n_walks, uint64_t seed, float* out_u,
+              float* out_grad, double* out_stats, const float* grad_u, float* out_dx, double* out_dsigma,
+              double* out_dg, const wos_options* opt, hipStream_t st, int force_upw, int force_gm)
+{
+    wos_options o;
+    int rc = read_opts(opt, o);
+    if (rc) return rc;
+    if (o.flags & WOS_FP64) return fail(WOS_ENOTSUP, "the batched kernel computes in FP32 only");
+    if (n_envs < 0 || (n_envs > 0 && (!envs || !q_offsets || !sigma || !eps || !n_walks)))
+        return fail(WOS_EINVAL, "envs, q_offsets, sigma, eps and n_walks are required");
+    if (n_envs == 0) return WOS_OK;
+    for (int e = 0; e < n_envs; ++e)
+        if (n_walks[e] < 1 || n_walks[e] > (int64_t)1 << 31) return fail(WOS_EINVAL, "n_walks[%d] must be in [1, 2^31]", e);
+    if (q_offsets[0] != 0) return fail(WOS_EINVAL, "q_offsets[0] must be 0");
+    for (int e = 0; e < n_envs; ++e) {
+        if (!envs[e]) return fail(WOS_EINVAL, "envs[%d] is NULL", e);
+        if (q_offsets[e + 1] < q_offsets[e]) return fail(WOS_EINVAL, "q_offsets must be non-decreasing");
+        if ((rc = check_device(envs[e]))) return rc;
+    }
+    const int64_t sumQ = q_offsets[n_envs];
+    if (sumQ > 0 && (!queries || !out_u)) return fail(WOS_EINVAL, "queries and out_u are required");
+    const bool bwd = grad_u != nullptr;
+    if (bwd && (!out_dx || !out_dsigma || !out_dg))
+        return fail(WOS_EINVAL, "out_dx, out_dsigma and out_dg are required with grad_u");
+    std::vector<EnvP<float>> hp(n_envs);
+    for (int e = 0; e < n_envs; ++e)
+        if ((rc = make_env<float>(envs[e], sigma[e], eps[e], seed, (uint32_t)e, o.max_steps, hp[e]))) return rc;
+
+    BatchLayout L;
+    plan_batch(envs, q_offsets, n_envs, n_walks, kBatchStride, force_upw, force_gm, L);
+
+    Scratch S(st);
+    // one upload: [EnvP x n_envs][BatchEnv x n_envs]
+    const size_t env_bytes = hp.size() * sizeof(EnvP<float>);
+    const size_t tab_bytes = env_bytes + L.benv.size() * sizeof(BatchEnv);
+    std::vector<unsigned char> host_tab(tab_bytes);
+    std::memcpy(host_tab.data(), hp.data(), env_bytes);
+    std::memcpy(host_tab.data() + env_bytes, L.benv.data(), L.benv.size() * sizeof(BatchEnv));
+    unsigned char* d_tab;
+    double* partials;
+    unsigned* counter;
+    if ((rc = S.get(&d_tab, tab_bytes)) || (rc = S.get(&partials, (size_t)L.total_units * nacc(kMaxDim))) ||
+        (rc = S.get(&counter, 1)))
+        return rc;
+    if ((rc = upload(d_tab, host_tab.data(), tab_bytes, st))) return rc;
+    const EnvP<float>* d_env = (const EnvP<float>*)d_tab;
+    const BatchEnv* d_benv = (const BatchEnv*)(d_tab + env_bytes);
+    WOS_HIP(launch_fill_u32(counter, 1, 0u, st), "fill");
+    WOS_HIP(launch_persistent(bwd, L.grid, 256, d_env, d_benv, n_envs, queries, L.total_units,
+                              (uint32_t)seed, (uint32_t)(seed >> 32), nullptr, counter, partials, st),
+            "persistent walk kernel");
+    WOS_HIP(launch_finalize_batch(bwd, d_benv, n_envs, partials, grad_u, out_u, out_grad, kBatchStride,
+                                  out_stats, out_dx, out_dsigma, out_dg, counter, st),
+            "batch finalize");
+    return WOS_OK;
+}
+
+}  // namespace
+
+// ==========================================================================
+// C ABI
+// ==========================================================================
+extern "C" {
+
+const char* wos_last_error(void) { return g_err.c_str(); }
+
+int wos_create_domain(int d, const wos_spheres* spheres, const wos_boxes* boxes, const wos_ball* goal,
+                      const wos_outer* outer, const wos_bdata* bdata, wos_domain** out)
+{
+    if (!out) return fail(WOS_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (d < WOS_MIN_DIM || d > WOS_MAX_DIM) return fail(WOS_EDIM, "d = %d outside [%d, %d]", d, WOS_MIN_DIM, WOS_MAX_DIM);
+    if (!outer || !bdata) return fail(WOS_EINVAL, "outer and bdata are required");
+    const int64_t ns = spheres ? spheres->n : 0, nb = boxes ? boxes->n : 0;
+    if (ns < 0 || nb < 0 || ns > (1 << 24) || nb > (1 << 24)) return fail(WOS_EINVAL, "bad obstacle counts");
+    if (ns > 0 && (!spheres->centers || !spheres->radii)) return fail(WOS_EINVAL, "sphere arrays are NULL");
+    if (nb > 0 && (!boxes->centers || !boxes->half_widths)) return fail(WOS_EINVAL, "box arrays are NULL");
+    if (ns > 0 && (!finite_all(spheres->centers, ns * d) || !finite_all(spheres->radii, ns)))
+        return fail(WOS_EINVAL, "non-finite sphere data");
+    if (nb > 0 && (!finite_all(boxes->centers, nb * d) || !finite_all(boxes->half_widths, nb * d)))
+        return fail(WOS_EINVAL, "non-finite box data");
+    for (int64_t j = 0; j < ns; ++j)
+        if (spheres->radii[j] < 0) return fail(WOS_EINVAL, "negative sphere radius");
+    for (int64_t j = 0; j < nb * d; ++j)
+        if (boxes->half_widths[j] < 0) return fail(WOS_EINVAL, "negative box half-width");
+    if (bdata->mode < 0 || bdata->mode > 2) return fail(WOS_EINVAL, "unknown boundary-data mode %d", bdata->mode);
+    if (bdata->mode != 0 && !bdata->a_or_k) return fail(WOS_EINVAL, "a_or_k is required for mode %d", bdata->mode);
+
+    wos_domain* D = new wos_domain();
+    D->d = d;
+    D->n_sph = ns;
+    D->n_box = nb;
+    if (goal) {
+        if (!goal->center || !(goal->radius > 0) || !finite_all(goal->center, d) || !std::isfinite(goal->radius)) {
+            delete D;
+            return fail(WOS_EINVAL, "bad goal ball");
+        }
+        D->has_goal = true;
+        for (int i = 0; i < d; ++i) D->goal_c[i] = goal->center[i];
+        D->goal_r = goal->radius;
+    }
+    D->outer_kind = outer->kind;
+    if (outer->kind == WOS_OUTER_BOX) {
+        if (!outer->lo || !outer->hi || !finite_all(outer->lo, d) || !finite_all(outer->hi, d)) {
+            delete D;
+            return fail(WOS_EINVAL, "bad outer box");
+        }
+        double rmax = INFINITY;
+        for (int i = 0; i < d; ++i) {
+            if (!(outer->hi[i] > outer->lo[i])) {
+                delete D;
+                return fail(WOS_EINVAL, "outer box needs hi > lo");
+            }
+            D->lo[i] = outer->lo[i];
+            D->hi[i] = outer->hi[i];
+            rmax = std::min(rmax, 0.5 * (outer->hi[i] - outer->lo[i]));
+        }
+        D->r_max = rmax;
+    } else if (outer->kind == WOS_OUTER_BALL) {
+        if (!outer->center || !(outer->radius > 0) || !finite_all(outer->center, d) || !std::isfinite(outer->radius)) {
+            delete D;
+            return fail(WOS_EINVAL, "bad outer ball");
+        }
+        for (int i = 0; i < d; ++i) D->oc[i] = outer->center[i];
+        D->orad = outer->radius;
+        D->r_max = outer->radius;
+    } else {
+        delete D;
+        return fail(WOS_EINVAL, "unknown outer kind %d", outer->kind);
+    }
+    D->mode = bdata->mode;
+    D->g_goal = bdata->g_goal;
+    D->g_obs = bdata->g_obstacle;
+    D->g_outer = bdata->g_outer;
+    D->b = bdata->b;
+    if (bdata->mode != 0)
+        for (int i = 0; i < d; ++i) D->ak[i] = bdata->a_or_k[i];
+    if (!std::isfinite(D->g_goal) || !std::isfinite(D->g_obs) || !std::isfinite(D->g_outer) || !std::isfinite(D->b) ||
+        !finite_all(D->ak, d)) {
+        delete D;
+        return fail(WOS_EINVAL, "non-finite boundary data");
+    }
+
+    // device tables, FP32 and FP64, padded rows
+    const int ss = sph_stride(d), bs = box_stride(d);
+    std::vector<float> sf((size_t)std::max<int64_t>(ns, 1) * ss, 0.f);
+    std::vector<double> sd((size_t)std::max<int64_t>(ns, 1) * ss, 0.0);
+    for (int64_t j = 0; j < ns; ++j) {
+        for (int i = 0; i < d; ++i) {
+            sd[j * ss + i] = spheres->centers[j * d + i];
+            sf[j * ss + i] = (float)spheres->centers[j * d + i];
+        }
+        sd[j * ss + d] = spheres->radii[j];
+        sf[j * ss + d] = (float)spheres->radii[j];
+    }
+    std::vector<float> bf((size_t)std::max<int64_t>(nb, 1) * bs, 0.f);
+    std::vector<double> bd((size_t)std::max<int64_t>(nb, 1) * bs, 0.0);
+    for (int64_t j = 0; j < nb; ++j) {
+        for (int i = 0; i < d; ++i) {
+            bd[j * bs + i] = boxes->centers[j * d + i];
+            bf[j * bs + i] = (float)boxes->centers[j * d + i];
+            bd[j * bs + d + i] = boxes->half_widths[j * d + i];
+            bf[j * bs + d + i] = (float)boxes->half_widths[j * d + i];
+        }
+    }
+    hipError_t e = hipGetDevice(&D->device);
+    if (e == hipSuccess) e = hipMalloc(&D->sph_f, sf.size() * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc(&D->sph_d, sd.size() * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&D->box_f, bf.size() * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc(&D->box_d, bd.size() * sizeof(double));
+    if (e == hipSuccess) e = hipMemcpy(D->sph_f, sf.data(), sf.size() * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(D->sph_d, sd.data(), sd.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(D->box_f, bf.data(), bf.size() * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(D->box_d, bd.data(), bd.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        wos_destroy_domain(D);
+        return fail(e == hipErrorOutOfMemory ? WOS_ENOMEM : WOS_EHIP, "domain upload: %s", hipGetErrorString(e));
+    }
+    *out = D;
+    return WOS_OK;
+}
+
+void wos_destroy_domain(wos_domain* D)
+{
+    if (!D) return;
+    (void)hipFree(D->sph_f);
+    (void)hipFree(D->sph_d);
+    (void)hipFree(D->box_f);
+    (void)hipFree(D->box_d);
+    delete D;
+}
+
+int wos_domain_dim(const wos_domain* D) { return D ? D->d : fail(WOS_EINVAL, "domain is NULL"); }
+
+static int estimate_impl(const wos_domain* D, const void* queries, int64_t Q, int64_t n_walks, double sigma,
+                         double eps, uint64_t seed, void* out_u, void* out_grad, double* out_stats,
+                         const void* grad_u, void* out_dx, double* out_dsigma, double* out_dg, double* out_dq,
+                         const wos_options* opt, hipStream_t st, bool bwd)
+{
+    if (!D) return fail(WOS_EINVAL, "domain is NULL");
+    wos_options o;
+    int rc = read_opts(opt, o);
+    if (rc) return rc;
+    if ((rc = check_device(D))) return rc;
+    if (Q < 0 || Q > ((int64_t)1 << 32)) return fail(WOS_EINVAL, "n_queries out of range");
+    if (n_walks < 1 || n_walks > ((int64_t)1 << 31)) return fail(WOS_EINVAL, "n_walks must be in [1, 2^31]");
+    if (bwd) {
+        if (!out_dx || !out_dsigma || !out_dg) return fail(WOS_EINVAL, "out_dx, out_dsigma and out_dg are required");
+        if (Q > 0 && !grad_u) return fail(WOS_EINVAL, "grad_u is required");
+    } else if (Q > 0 && !out_u) {
+        return fail(WOS_EINVAL, "out_u is required");
+    }
+    if (Q > 0 && !queries) return fail(WOS_EINVAL, "queries is NULL");
+    const int d = D->d;
+    const int32_t chunks = (int32_t)((n_walks + kWave - 1) / kWave);
+    Scratch S(st);
+    double* partials = nullptr;
+    double* prod = nullptr;
+    if ((rc = S.get(&partials, (size_t)std::max<int64_t>(Q, 1) * chunks * nacc(d)))) return rc;
+    if (bwd && (rc = S.get(&prod, (size_t)std::max<int64_t>(Q, 1) * 2))) return rc;
+    if (o.flags & WOS_FP64) {
+        EnvP<double> p;
+        if ((rc = make_env<double>(D, sigma, eps, seed, o.env_id, o.max_steps, p))) return rc;
+        if (Q == 0) {
+            if (bwd) {
+                WOS_HIP(launch_fill_f64(out_dsigma, 1, 0.0, st), "fill");
+                WOS_HIP(launch_fill_f64(out_dg, 1, 0.0, st), "fill");
+            }
+            return WOS_OK;
+        }
+        double* uo = (double*)out_u;
+        double* uscratch = nullptr;
+        if (bwd && !uo) {
+            if ((rc = S.get(&uscratch, (size_t)Q))) return rc;
+            uo = uscratch;
+        }
+        EnvP<double>* pd;
+        if ((rc = S.get(&pd, 1)) || (rc = upload(pd, &p, sizeof(p), st))) return rc;
+        WOS_HIP(launch_plain<double>(d, bwd, pd, (const double*)queries, Q, n_walks, 0, 0, nullptr, partials, nullptr, st),
+                "plain walk kernel");
+        WOS_HIP(launch_finalize_plain<double>(d, bwd, partials, Q, chunks, n_walks, uo, (double*)out_grad, out_stats,
+                                              (const double*)grad_u, (double*)out_dx, out_dq, prod, st),
+                "finalize");
+    } else {
+        EnvP<float> p;
+        if ((rc = make_env<float>(D, sigma, eps, seed, o.env_id, o.max_steps, p))) return rc;
+        if (Q == 0) {
+            if (bwd) {
+                WOS_HIP(launch_fill_f64(out_dsigma, 1, 0.0, st), "fill");
+                WOS_HIP(launch_fill_f64(out_dg, 1, 0.0, st), "fill");
+            }
+            return WOS_OK;
+        }
+        float* uo = (float*)out_u;
+        float* uscratch = nullptr;
+        if (bwd && !uo) {
+            if ((rc = S.get(&uscratch, (size_t)Q))) return rc;
+            uo = uscratch;
+        }
+        EnvP<float>* pd;
+        if ((rc = S.get(&pd, 1)) || (rc = upload(pd, &p, sizeof(p), st))) return rc;
+        WOS_HIP(launch_plain<float>(d, bwd, pd, (const float*)queries, Q, n_walks, 0, 0, nullptr, partials, nullptr, st),
+                "plain walk kernel");
+        WOS_HIP(launch_finalize_plain<float>(d, bwd, partials, Q, chunks, n_walks, uo, (float*)out_grad, out_stats,
+                                             (const float*)grad_u, (float*)out_dx, out_dq, prod, st),
+                "finalize");
+    }
+    if (bwd) WOS_HIP(launch_reduce_pairs(prod, Q, out_dsigma, out_dg, st), "reduce");
+    return WOS_OK;
+}
+
+int wos_estimate(const wos_domain* dom, const void* queries, int64_t n_queries, int64_t n_walks, double sigma,
+                 double eps, uint64_t seed, void* out_u, void* out_grad, double* out_stats,
+                 const wos_options* opt, void* stream)
+{
+    return estimate_impl(dom, queries, n_queries, n_walks, sigma, eps, seed, out_u, out_grad, out_stats, nullptr,
+                         nullptr, nullptr, nullptr, nullptr, opt, (hipStream_t)stream, false);
+}
+
+int wos_backward(const wos_domain* dom, const void* queries, int64_t n_queries, int64_t n_walks, double sigma,
+                 double eps, uint64_t seed, const void* grad_u, void* out_dx, double* out_dsigma,
+                 double* out_dg_goal, double* out_dq, const wos_options* opt, void* stream)
+{
+    return estimate_impl(dom, queries, n_queries, n_walks, sigma, eps, seed, nullptr, nullptr, nullptr, grad_u,
+                         out_dx, out_dsigma, out_dg_goal, out_dq, opt, (hipStream_t)stream, true);
+}
+
+int wos_estimate_batch(const wos_domain* const* envs, int n_envs, const float* queries, const int64_t* q_offsets,
+                       const double* sigma, const double* eps, const int64_t* n_walks, uint64_t seed, float* out_u,
+                       float* out_grad, double* out_stats, const float* grad_u, float* out_dx, double* out_dsigma,
+                       double* out_dg, const wos_options* opt, void* stream)
+{
+    return run_batch(envs, n_envs, queries, q_offsets, sigma, eps, n_walks, seed, out_u, out_grad, out_stats,
+                     grad_u, out_dx, out_dsigma, out_dg, opt, (hipStream_t)stream, 0, 0);
+}
+
+int wos_debug_walks(const wos_domain* D, const double* query, uint32_t q_index, int64_t w0, int64_t n, double sigma,
+                    double eps, uint64_t seed, const wos_options* opt, double* out_records)
+{
+    if (!D || !query || !out_records) return fail(WOS_EINVAL, "domain, query and out_records are required");
+    wos_options o;
+    int rc = read_opts(opt, o);
+    if (rc) return rc;
+    if ((rc = check_device(D))) return rc;
+    if (n < 1 || w0 < 0 || w0 + n > ((int64_t)1 << 32)) return fail(WOS_EINVAL, "bad walk range");
+    const int d = D->d;
+    const int32_t chunks = (int32_t)((n + kWave - 1) / kWave);
+    void* dq = nullptr;
+    double* part = nullptr;
+    double* rec = nullptr;
+    const size_t esz = (o.flags & WOS_FP64) ? sizeof(double) : sizeof(float);
+    hipError_t e = hipMalloc(&dq, d * esz);
+    if (e == hipSuccess) e = hipMalloc(&part, (size_t)chunks * nacc(d) * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&rec, (size_t)n * (d + 7) * sizeof(double));
+    if (e == hipSuccess) {
+        if (o.flags & WOS_FP64) {
+            e = hipMemcpy(dq, query, d * sizeof(double), hipMemcpyHostToDevice);
+            EnvP<double> p;
+            rc = make_env<double>(D, sigma, eps, seed, o.env_id, o.max_steps, p);
+            void* pd = nullptr;
+            if (!rc && e == hipSuccess) e = hipMalloc(&pd, sizeof(p));
+            if (!rc && e == hipSuccess) e = hipMemcpy(pd, &p, sizeof(p), hipMemcpyHostToDevice);
+            if (!rc && e == hipSuccess)
+                e = launch_plain<double>(d, true, (const EnvP<double>*)pd, (const double*)dq, 1, n, w0, q_index, nullptr,
+                                         part, rec, nullptr);
+            if (e == hipSuccess) e = hipDeviceSynchronize();
+            (void)hipFree(pd);
+        } else {
+            float qf[kMaxDim];
+            for (int i = 0; i < d; ++i) qf[i] = (float)query[i];
+            e = hipMemcpy(dq, qf, d * sizeof(float), hipMemcpyHostToDevice);
+            EnvP<float> p;
+            rc = make_env<float>(D, sigma, eps, seed, o.env_id, o.max_steps, p);
+            void* pd = nullptr;
+            if (!rc && e == hipSuccess) e = hipMalloc(&pd, sizeof(p));
+            if (!rc && e == hipSuccess) e = hipMemcpy(pd, &p, sizeof(p), hipMemcpyHostToDevice);
+            if (!rc && e == hipSuccess)
+                e = launch_plain<float>(d, true, (const EnvP<float>*)pd, (const float*)dq, 1, n, w0, q_index, nullptr,
+                                        part, rec, nullptr);
+            if (e == hipSuccess) e = hipDeviceSynchronize();
+            (void)hipFree(pd);
+        }
+    }
+    if (e == hipSuccess && !rc) e = hipDeviceSynchronize();
+    if (e == hipSuccess && !rc) e = hipMemcpy(out_records, rec, (size_t)n * (d + 7) * sizeof(double), hipMemcpyDeviceToHost);
+    (void)hipFree(dq);
+    (void)hipFree(part);
+    (void)hipFree(rec);
+    if (rc) return rc;
+    if (e != hipSuccess) return hip_fail(e, "debug walks");
+    return WOS_OK;
+}
+
+// ----------------------------------------------------------------------------
+// Planning loop
+// ----------------------------------------------------------------------------
+}  // extern "C"
+
+struct wos_plan {
+    int d = 0;
+    int64_t S = 0;
+    hipStream_t st = nullptr;
+    bool own_stream = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    float* x = nullptr;
+    float* u = nullptr;
+    float* grad = nullptr;
+    float* ubar = nullptr;
+    float* dx = nullptr;
+    double* dsig = nullptr;
+    double* dg = nullptr;
+    double* partials = nullptr;
+    double* path_len = nullptr;
+    int32_t* stalls = nullptr;
+    int32_t* status = nullptr;
+    uint64_t* step = nullptr;
+    unsigned* counter = nullptr;
+    EnvP<float>* env = nullptr;
+    BatchEnv* benv = nullptr;
+    EnvP<float> henv;
+};
+
+static void plan_free(wos_plan* P)
+{
+    if (!P) return;
+    if (P->exec) (void)hipGraphExecDestroy(P->exec);
+    if (P->graph) (void)hipGraphDestroy(P->graph);
+    void* bufs[] = {P->u, P->grad, P->ubar, P->dx, P->dsig, P->dg, P->partials, P->path_len,
+                    P->stalls, P->status, P->step, P->counter, P->env, P->benv};
+    for (void* b : bufs)
+        if (b) (void)hipFree(b);
+    if (P->own_stream && P->st) (void)hipStreamDestroy(P->st);
+    delete P;
+}
+
+extern "C" {
+
+int wos_plan_create(const wos_domain* D, float* x, int64_t n_starts, int64_t n_walks, double sigma, double eps,
+                    double s_ub, uint64_t seed, const wos_options* opt, void* stream, wos_plan** out)
+{
+    if (!out) return fail(WOS_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!D || !x) return fail(WOS_EINVAL, "domain and x are required");
+    wos_options o;
+    int rc = read_opts(opt, o);
+    if (rc) return rc;
+    if (o.flags & WOS_FP64) return fail(WOS_ENOTSUP, "the planning loop computes in FP32 only");
+    if ((rc = check_device(D))) return rc;
+    if (n_starts < 1 || n_starts > (1 << 24)) return fail(WOS_EINVAL, "n_starts out of range");
+    if (n_walks < 1 || n_walks > ((int64_t)1 << 31)) return fail(WOS_EINVAL, "n_walks must be in [1, 2^31]");
+    if (!(s_ub > 0) || !std::isfinite(s_ub)) return fail(WOS_EINVAL, "s_ub must be finite and > 0");
+    wos_plan* P = new wos_plan();
+    P->d = D->d;
+    P->S = n_starts;
+    P->x = x;
+    if ((rc = make_env<float>(D, sigma, eps, seed, o.env_id, o.max_steps, P->henv))) {
+        delete P;
+        return rc;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = hipSuccess;
+    if (!st) {
+        e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+        P->own_stream = true;
+    }
+    P->st = st;
+    const wos_domain* envs[1] = {D};
+    const int64_t qoff[2] = {0, n_starts};
+    const int64_t nw[1] = {n_walks};
+    BatchLayout L;
+    plan_batch(envs, qoff, 1, nw, D->d, 0, 0, L);
+    const int64_t S = n_starts;
+    if (e == hipSuccess) e = hipMalloc(&P->u, S * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc(&P->grad, S * kBatchStride * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc(&P->ubar, S * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc(&P->dx, S * kBatchStride * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc(&P->dsig, sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&P->dg, sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&P->partials, (size_t)std::max<int64_t>(L.total_units, 1) * nacc(kMaxDim) * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&P->path_len, S * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&P->stalls, S * sizeof(int32_t));
+    if (e == hipSuccess) e = hipMalloc(&P->status, S * sizeof(int32_t));
+    if (e == hipSuccess) e = hipMalloc(&P->step, sizeof(uint64_t));
+    if (e == hipSuccess) e = hipMalloc(&P->counter, sizeof(unsigned));
+    if (e == hipSuccess) e = hipMalloc(&P->env, sizeof(EnvP<float>));
+    if (e == hipSuccess) e = hipMalloc(&P->benv, sizeof(BatchEnv));
+    if (e == hipSuccess) e = hipMemcpy(P->env, &P->henv, sizeof(EnvP<float>), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(P->benv, L.benv.data(), sizeof(BatchEnv), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = launch_fill_f64(P->path_len, S, 0.0, st);
+    if (e == hipSuccess) e = launch_fill_u32((unsigned*)P->stalls, S, 0u, st);
+    if (e == hipSuccess) e = launch_fill_u32((unsigned*)P->status, S, 0u, st);
+    if (e == hipSuccess) e = launch_fill_u32((unsigned*)P->step, 2, 0u, st);
+    if (e == hipSuccess) e = launch_fill_u32(P->counter, 1, 0u, st);
+    if (e == hipSuccess) e = launch_fill_u32((unsigned*)P->ubar, S, 0x3f800000u, st);  // upstream weights 1.0f
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        plan_free(P);
+        return hip_fail(e, "plan set-up");
+    }
+    // capture [fused forward + backward walks, finalize, update]
+    e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        hipError_t e1 = launch_persistent(true, L.grid, 256, P->env, P->benv, 1, x, L.total_units,
+                                          P->henv.key0, P->henv.key1, P->step, P->counter, P->partials, st);
+        hipError_t e2 = launch_finalize_batch(true, P->benv, 1, P->partials, P->ubar, P->u, P->grad,
+                                              kBatchStride, nullptr, P->dx, P->dsig, P->dg, P->counter, st);
+        hipError_t e3 = launch_plan_update(D->d, P->env, x, S, P->grad, kBatchStride, (float)s_ub, P->path_len,
+                                           P->stalls, P->status, P->step, st);
+        e = hipStreamEndCapture(st, &P->graph);
+        if (e == hipSuccess) e = (e1 != hipSuccess) ? e1 : (e2 != hipSuccess) ? e2 : e3;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&P->exec, P->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        plan_free(P);
+        return hip_fail(e, "plan graph capture");
+    }
+    *out = P;
+    return WOS_OK;
+}
+
+int wos_plan_step(wos_plan* P, int n_steps)
+{
+    if (!P) return fail(WOS_EINVAL, "plan is NULL");
+    if (n_steps < 0) return fail(WOS_EINVAL, "n_steps < 0");
+    for (int i = 0; i < n_steps; ++i) WOS_HIP(hipGraphLaunch(P->exec, P->st), "hipGraphLaunch");
+    return WOS_OK;
+}
+
+int wos_plan_buffers(wos_plan* P, float** u, float** grad, double** path_len, int32_t** stalls, int32_t** status,
+                     uint64_t** step)
+{
+    if (!P) return fail(WOS_EINVAL, "plan is NULL");
+    if (u) *u = P->u;
+    if (grad) *grad = P->grad;
+    if (path_len) *path_len = P->path_len;
+    if (stalls) *stalls = P->stalls;
+    if (status) *status = P->status;
+    if (step) *step = P->step;
+    return WOS_OK;
+}
+
+int wos_plan_read(wos_plan* P, float* u, float* grad, double* path_len, int32_t* stalls, int32_t* status,
+                  uint64_t* step)
+{
+    if (!P) return fail(WOS_EINVAL, "plan is NULL");
+    WOS_HIP(hipStreamSynchronize(P->st), "plan sync");
+    const int64_t S = P->S;
+    if (u) WOS_HIP(hipMemcpy(u, P->u, S * sizeof(float), hipMemcpyDeviceToHost), "plan read");
+    if (grad) WOS_HIP(hipMemcpy(grad, P->grad, S * kBatchStride * sizeof(float), hipMemcpyDeviceToHost), "plan read");
+    if (path_len) WOS_HIP(hipMemcpy(path_len, P->path_len, S * sizeof(double), hipMemcpyDeviceToHost), "plan read");
+    if (stalls) WOS_HIP(hipMemcpy(stalls, P->stalls, S * sizeof(int32_t), hipMemcpyDeviceToHost), "plan read");
+    if (status) WOS_HIP(hipMemcpy(status, P->status, S * sizeof(int32_t), hipMemcpyDeviceToHost), "plan read");
+    if (step) WOS_HIP(hipMemcpy(step, P->step, sizeof(uint64_t), hipMemcpyDeviceToHost), "plan read");
+    return WOS_OK;
+}
+
+void wos_plan_destroy(wos_plan* P)
+{
+    if (!P) return;
+    if (P->st) (void)hipStreamSynchronize(P->st);
+    plan_free(P);
+}
+
+// ----------------------------------------------------------------------------
+// Autotuner
+// ----------------------------------------------------------------------------
+int wos_set_autotune_cache(const char* cache_path)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    load_tune_locked(cache_path);
+    return WOS_OK;
+}
+
+int wos_autotune(int d, int64_t M, int64_t Q, int64_t n_walks, const char* cache_path)
+{
+    if (d < WOS_MIN_DIM || d > WOS_MAX_DIM) return fail(WOS_EDIM, "d = %d outside [2, 8]", d);
+    if (M < 0 || Q < 1 || n_walks < 1 || !cache_path) return fail(WOS_EINVAL, "bad autotune arguments");
+    // synthetic scene: M spheres r in [0.1, 0.4] in [-pi, pi]^d (64-bit LCG)
+    uint64_t s = 0x9E3779B97F4A7C15ull ^ ((uint64_t)d << 32) ^ (uint64_t)M;
+    auto rnd = [&]() {
+        s = s * 6364136223846793005ull + 1442695040888963407ull;
+        return (double)(s >> 11) * 0x1p-53;
+    };
+    const double pi = 3.14159265358979323846;
+    std::vector<double> c((size_t)std::max<int64_t>(M, 1) * d), r((size_t)std::max<int64_t>(M, 1));
+    for (int64_t j = 0; j < M; ++j) {
+        for (int i = 0; i < d; ++i) c[j * d + i] = (2 * rnd() - 1) * pi;
+        r[j] = 0.1 + 0.3 * rnd();
+    }
+    std::vector<double> lo(d, -pi), hi(d, pi), gc(d, 0.0);
+    wos_spheres sp{M, c.data(), r.data()};
+    wos_ball goal{gc.data(), 0.15};
+    wos_outer ob{WOS_OUTER_BOX, lo.data(), hi.data(), nullptr, 0};
+    wos_bdata bdv{WOS_BDATA_CLASS, 1.0, 0.0, 0.0, nullptr, 0.0};
+    wos_domain* D = nullptr;
+    int rc = wos_create_domain(d, &sp, nullptr, &goal, &ob, &bdv, &D);
+    if (rc) return rc;
+    std::vector<float> hq((size_t)Q * kBatchStride, 0.f);
+    for (int64_t q = 0; q < Q; ++q)
+        for (int i = 0; i < d; ++i) hq[q * kBatchStride + i] = (float)((2 * rnd() - 1) * (pi - 0.05));
+    float *dq = nullptr, *du = nullptr, *dgr = nullptr, *dub = nullptr, *ddx = nullptr;
+    double *dds = nullptr, *ddg = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipMalloc(&dq, hq.size() * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc(&du, Q * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc(&dgr, Q * kBatchStride * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc(&dub, Q * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc(&ddx, Q * kBatchStride * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc(&dds, sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&ddg, sizeof(double));
+    if (e == hipSuccess) e = hipMemcpy(dq, hq.data(), hq.size() * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = launch_fill_u32((unsigned*)dub, Q, 0x3f800000u, nullptr);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    Tune best;
+    float best_ms = INFINITY;
+    const int upws[] = {1, 2, 4, 8, 16};
+    const int gms[] = {1, 2};
+    const wos_domain* envs[1] = {D};
+    const int64_t qoff[2] = {0, Q};
+    const int64_t nw[1] = {n_walks};
+    const double sig = 2.0, ep = 1e-4;
+    for (int gm : gms) {
+        for (int upw : upws) {
+            if (e != hipSuccess || rc) break;
+            // warm-up then one timed launch
+            for (int rep = 0; rep < 2 && !rc && e == hipSuccess; ++rep) {
+                if (rep == 1) e = hipEventRecord(e0, nullptr);
+                rc = run_batch(envs, 1, dq, qoff, &sig, &ep, nw, 1234 + rep, du, dgr, nullptr, dub, ddx, dds, ddg,
+                               nullptr, nullptr, upw, gm);
+                if (rep == 1 && e == hipSuccess) e = hipEventRecord(e1, nullptr);
+            }
+            if (e == hipSuccess && !rc) e = hipEventSynchronize(e1);
+            float ms = 0;
+            if (e == hipSuccess && !rc) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e == hipSuccess && !rc && ms < best_ms) {
+                best_ms = ms;
+                best = Tune{upw, gm};
+            }
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    void* bufs[] = {dq, du, dgr, dub, ddx, dds, ddg};
+    (void)hipDeviceSynchronize();
+    for (void* b : bufs)
+        if (b) (void)hipFree(b);
+    wos_destroy_domain(D);
+    if (rc) return rc;
+    if (e != hipSuccess) return hip_fail(e, "autotune");
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    if (!g_tune_loaded || g_tune_path != cache_path) load_tune_locked(cache_path);
+    g_tune[tune_key(d, M, Q)] = best;
+    return save_tune_locked(cache_path);
+}
+
+}  // extern "C"

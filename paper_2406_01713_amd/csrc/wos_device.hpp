@@ -1,0 +1,495 @@
+// wos_device.hpp -- device building blocks of the Walk-on-Spheres walk kernels
+// for gfx950: counter-based Philox random numbers, uniform directions on the
+// sphere, the distance-to-boundary loop over wave-uniform obstacle tables,
+// closest points and boundary data, the screening-weight series and one walk
+// iteration.  Internal to libwos.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "wos_params.hpp"
+
+namespace wos {
+
+// Read-only tables are accessed through the constant address space: with a
+// wave-uniform index the compiler turns every read into a scalar load (one
+// fetch per wave through the scalar cache, operands in SGPRs).
+template <typename T>
+using cptr = const __attribute__((address_space(4))) T*;
+
+template <typename T>
+__device__ __forceinline__ cptr<T> to_const(const T* p)
+{
+    return (cptr<T>)p;
+}
+
+// An empty asm that claims to rewrite a scalar value.  Placed right before a
+// use, it stops the compiler from hoisting the loads (or key schedule) that
+// depend on the value out of the walk loop and pinning them in scalar
+// registers for the whole loop; they are re-read from the scalar cache
+// instead, which keeps the hot obstacle loop free of scalar-register spills.
+template <typename T>
+__device__ __forceinline__ cptr<T> fresh(cptr<T> p)
+{
+    asm volatile("" : "+s"(p));
+    return p;
+}
+
+__device__ __forceinline__ uint32_t fresh(uint32_t v)
+{
+    asm volatile("" : "+s"(v));
+    return v;
+}
+
+template <typename T>
+using cenv = cptr<EnvP<T>>;
+
+// ------------------------------------------------------------------------
+// Precision-specific math.  FP32 uses the hardware instructions directly
+// (v_sqrt_f32, v_rcp_f32, v_rsq_f32, v_log_f32 = log2, v_sin/v_cos_f32 whose
+// argument is in turns); FP64 uses the device math library.
+// ------------------------------------------------------------------------
+template <typename T>
+struct Math;
+
+template <>
+struct Math<float> {
+    static __device__ __forceinline__ float inf() { return __builtin_huge_valf(); }
+    static __device__ __forceinline__ float sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+    static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+    static __device__ __forceinline__ float rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
+    static __device__ __forceinline__ float fma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+    static __device__ __forceinline__ float min(float a, float b) { return __builtin_fminf(a, b); }
+    static __device__ __forceinline__ float max(float a, float b) { return __builtin_fmaxf(a, b); }
+    static __device__ __forceinline__ float abs(float a) { return __builtin_fabsf(a); }
+    static __device__ __forceinline__ float exp(float x) { return __expf(x); }
+    // Box-Muller radius sqrt(-2 ln u) with ln u = ln 2 * log2 u
+    static __device__ __forceinline__ float bm_radius(float u)
+    {
+        return __builtin_amdgcn_sqrtf(-1.38629436111989061883f * __builtin_amdgcn_logf(u));
+    }
+    // sin and cos of 2 pi t
+    static __device__ __forceinline__ void sincos_turns(float t, float& s, float& c)
+    {
+        s = __builtin_amdgcn_sinf(t);
+        c = __builtin_amdgcn_cosf(t);
+    }
+    // (2 (x >> 9) + 1) 2^-24: exact in FP32
+    static __device__ __forceinline__ float uniform(uint32_t x)
+    {
+        return (float)(2u * (x >> 9) + 1u) * 0x1p-24f;
+    }
+};
+
+template <>
+struct Math<double> {
+    static __device__ __forceinline__ double inf() { return __builtin_huge_val(); }
+    static __device__ __forceinline__ double sqrt(double x) { return ::sqrt(x); }
+    static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+    static __device__ __forceinline__ double rsqrt(double x) { return 1.0 / ::sqrt(x); }
+    static __device__ __forceinline__ double fma(double a, double b, double c) { return __builtin_fma(a, b, c); }
+    static __device__ __forceinline__ double min(double a, double b) { return __builtin_fmin(a, b); }
+    static __device__ __forceinline__ double max(double a, double b) { return __builtin_fmax(a, b); }
+    static __device__ __forceinline__ double abs(double a) { return __builtin_fabs(a); }
+    static __device__ __forceinline__ double exp(double x) { return ::exp(x); }
+    static __device__ __forceinline__ double bm_radius(double u) { return ::sqrt(-2.0 * ::log(u)); }
+    static __device__ __forceinline__ void sincos_turns(double t, double& s, double& c)
+    {
+        ::sincospi(2.0 * t, &s, &c);
+    }
+    static __device__ __forceinline__ double uniform(uint32_t x)
+    {
+        return (double)(2u * (x >> 9) + 1u) * 0x1p-24;
+    }
+};
+
+// ------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
+// 32x32->64-bit products on words 0 and 2, word swap and xor with the round
+// key; the key is bumped by the Weyl constants after each round.  The key is
+// wave-uniform, so its schedule stays in scalar registers.
+// ------------------------------------------------------------------------
+__device__ __forceinline__ void philox4x32_10(uint32_t& c0, uint32_t& c1, uint32_t& c2, uint32_t& c3,
+                                              uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t lo0 = 0xD2511F53u * c0;
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c0);
+        const uint32_t lo1 = 0xCD9E8D57u * c2;
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2);
+        const uint32_t y0 = hi1 ^ c1 ^ k0;
+        const uint32_t y2 = hi0 ^ c3 ^ k1;
+        c0 = y0;
+        c1 = lo1;
+        c2 = y2;
+        c3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+}
+
+// Uniform direction on S^{D-1} for step k of walk (w, q, env) (Sec. IV: the
+// next point is uniform on the sphere of the largest empty ball).  Block j of
+// the step uses counter (2k + j, w, q, env); Box-Muller pair p uses words
+// 2p, 2p + 1; the normal vector is scaled to unit length.
+template <typename T, int D>
+__device__ __forceinline__ void direction(uint32_t k, uint32_t w, uint32_t q, uint32_t env,
+                                          uint32_t key0, uint32_t key1, T (&v)[D])
+{
+    constexpr int NP = (D + 1) / 2;
+    constexpr int NB = (NP + 1) / 2;
+    uint32_t words[4 * NB];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        uint32_t c0 = 2u * k + (uint32_t)j, c1 = w, c2 = q, c3 = env;
+        philox4x32_10(c0, c1, c2, c3, fresh(key0), fresh(key1));
+        words[4 * j + 0] = c0;
+        words[4 * j + 1] = c1;
+        words[4 * j + 2] = c2;
+        words[4 * j + 3] = c3;
+    }
+    T n[2 * NP];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        const T rho = Math<T>::bm_radius(Math<T>::uniform(words[2 * p]));
+        T s, c;
+        Math<T>::sincos_turns(Math<T>::uniform(words[2 * p + 1]), s, c);
+        n[2 * p] = rho * c;
+        n[2 * p + 1] = rho * s;
+    }
+    T n2 = n[0] * n[0];
+#pragma unroll
+    for (int i = 1; i < D; ++i) n2 = Math<T>::fma(n[i], n[i], n2);
+    const T inv = Math<T>::rsqrt(n2);
+#pragma unroll
+    for (int i = 0; i < D; ++i) v[i] = n[i] * inv;
+}
+
+// ------------------------------------------------------------------------
+// Distance to the boundary (Sec. V).  The obstacle loops are the hot loop of
+// the method: every walk step scans all obstacles of its environment.
+// ------------------------------------------------------------------------
+template <typename T, int D>
+__device__ __forceinline__ T sq_dist(const T (&x)[D], cptr<T> c)
+{
+    T t = x[0] - c[0];
+    T acc = t * t;
+#pragma unroll
+    for (int i = 1; i < D; ++i) {
+        t = x[i] - c[i];
+        acc = Math<T>::fma(t, t, acc);
+    }
+    return acc;
+}
+
+template <typename T, int D>
+__device__ __forceinline__ T sphere_dist(const T (&x)[D], cptr<T> row)
+{
+    return Math<T>::sqrt(sq_dist<T, D>(x, row)) - row[D];
+}
+
+template <typename T, int D>
+__device__ __forceinline__ T box_dist(const T (&x)[D], cptr<T> row)
+{
+    // signed distance: |max(q, 0)| + min(max_i q_i, 0), q = |x - c| - h
+    T out2 = 0, inside = -Math<T>::inf();
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        const T q = Math<T>::abs(x[i] - row[i]) - row[D + i];
+        const T qp = Math<T>::max(q, T(0));
+        out2 = Math<T>::fma(qp, qp, out2);
+        inside = Math<T>::max(inside, q);
+    }
+    return Math<T>::sqrt(out2) + Math<T>::min(inside, T(0));
+}
+
+template <typename T, int D>
+__device__ __forceinline__ T spheres_min(cptr<T> sph, int n, const T (&x)[D])
+{
+    constexpr int S = sph_stride(D);
+    T best = Math<T>::inf();
+#pragma unroll 4
+    for (int j = 0; j < n; ++j) best = Math<T>::min(best, sphere_dist<T, D>(x, sph + j * S));
+    return best;
+}
+
+template <typename T, int D>
+__device__ __forceinline__ T boxes_min(cptr<T> box, int n, const T (&x)[D])
+{
+    constexpr int S = box_stride(D);
+    T best = Math<T>::inf();
+#pragma unroll 2
+    for (int j = 0; j < n; ++j) best = Math<T>::min(best, box_dist<T, D>(x, box + j * S));
+    return best;
+}
+
+template <typename T, int D>
+__device__ __forceinline__ T outer_dist(cenv<T> p, const T (&x)[D])
+{
+    if (p->outer_kind == 0) {
+        T m = Math<T>::min(x[0] - p->lo[0], p->hi[0] - x[0]);
+#pragma unroll
+        for (int i = 1; i < D; ++i) m = Math<T>::min(m, Math<T>::min(x[i] - p->lo[i], p->hi[i] - x[i]));
+        return m;
+    }
+    T t = x[0] - p->oc[0];
+    T acc = t * t;
+#pragma unroll
+    for (int i = 1; i < D; ++i) {
+        t = x[i] - p->oc[i];
+        acc = Math<T>::fma(t, t, acc);
+    }
+    return p->orad - Math<T>::sqrt(acc);
+}
+
+// R = distance to the boundary; cls = first component attaining it in the
+// order goal, spheres, boxes, outer.
+template <typename T, int D>
+__device__ __forceinline__ T distance(cenv<T> p, const T (&x)[D], int& cls)
+{
+    const T ds = spheres_min<T, D>(to_const(p->sph), p->n_sph, x);
+    const T db = boxes_min<T, D>(to_const(fresh(p)->box), fresh(p)->n_box, x);
+    p = fresh(p);
+    T dg = Math<T>::inf();
+    if (p->has_goal) {
+        T t = x[0] - p->goal_c[0];
+        T acc = t * t;
+#pragma unroll
+        for (int i = 1; i < D; ++i) {
+            t = x[i] - p->goal_c[i];
+            acc = Math<T>::fma(t, t, acc);
+        }
+        dg = Math<T>::sqrt(acc) - p->goal_r;
+    }
+    const T dout = outer_dist<T, D>(p, x);
+    const T bo = Math<T>::min(db, dout);
+    const T rest = Math<T>::min(ds, bo);
+    cls = (dg <= rest) ? kGoal : (ds <= bo) ? kSphere : (db <= dout) ? kBox : kOuter;
+    return Math<T>::min(dg, rest);
+}
+
+// Closest boundary point xbar on the absorbing component (Fig. 2).  Sphere and
+// box indices are recovered by rescanning with the same distance code.
+template <typename T, int D>
+__device__ __forceinline__ void closest_point(cenv<T> p, const T (&x)[D], int cls, T (&xb)[D])
+{
+#pragma unroll
+    for (int i = 0; i < D; ++i) xb[i] = x[i];
+    if (cls == kOuter && p->outer_kind == 0) {
+        int im = 0;
+        bool hif = false;
+        T m = Math<T>::inf();
+        for (int i = 0; i < D; ++i) {
+            const T a = x[i] - p->lo[i], b = p->hi[i] - x[i];
+            if (a < m) { m = a; im = i; hif = false; }
+            if (b < m) { m = b; im = i; hif = true; }
+        }
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+            if (i == im) xb[i] = hif ? p->hi[i] : p->lo[i];
+        return;
+    }
+    T c[D];
+    T r;
+    if (cls == kBox) {
+        constexpr int S = box_stride(D);
+        cptr<T> tab = to_const(p->box);
+        int jm = 0;
+        T best = Math<T>::inf();
+        for (int j = 0; j < p->n_box; ++j) {
+            const T dj = box_dist<T, D>(x, tab + j * S);
+            if (dj < best) { best = dj; jm = j; }
+        }
+        cptr<T> row = tab + jm * S;
+        bool inside = true;
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+            if (Math<T>::abs(x[i] - row[i]) > row[D + i]) inside = false;
+        if (!inside) {
+#pragma unroll
+            for (int i = 0; i < D; ++i)
+                xb[i] = Math<T>::min(Math<T>::max(x[i], row[i] - row[D + i]), row[i] + row[D + i]);
+            return;
+        }
+        int im = 0;
+        T qm = -Math<T>::inf();
+        for (int i = 0; i < D; ++i) {
+            const T q = Math<T>::abs(x[i] - row[i]) - row[D + i];
+            if (q > qm) { qm = q; im = i; }
+        }
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+            if (i == im) xb[i] = row[i] + (x[i] >= row[i] ? row[D + i] : -row[D + i]);
+        return;
+    }
+    if (cls == kSphere) {
+        constexpr int S = sph_stride(D);
+        cptr<T> tab = to_const(p->sph);
+        int jm = 0;
+        T best = Math<T>::inf();
+        for (int j = 0; j < p->n_sph; ++j) {
+            const T dj = sphere_dist<T, D>(x, tab + j * S);
+            if (dj < best) { best = dj; jm = j; }
+        }
+#pragma unroll
+        for (int i = 0; i < D; ++i) c[i] = tab[jm * S + i];
+        r = tab[jm * S + D];
+    } else if (cls == kGoal) {
+#pragma unroll
+        for (int i = 0; i < D; ++i) c[i] = p->goal_c[i];
+        r = p->goal_r;
+    } else {
+#pragma unroll
+        for (int i = 0; i < D; ++i) c[i] = p->oc[i];
+        r = p->orad;
+    }
+    T n2 = 0;
+#pragma unroll
+    for (int i = 0; i < D; ++i) n2 = Math<T>::fma(x[i] - c[i], x[i] - c[i], n2);
+    if (n2 == T(0)) {
+#pragma unroll
+        for (int i = 0; i < D; ++i) xb[i] = c[i];
+        xb[0] = c[0] + r;
+        return;
+    }
+    const T s = r / Math<T>::sqrt(n2);
+#pragma unroll
+    for (int i = 0; i < D; ++i) xb[i] = c[i] + s * (x[i] - c[i]);
+}
+
+// Boundary data g at the closest point of the absorbing component.
+template <typename T, int D>
+__device__ __forceinline__ T boundary_value(cenv<T> p, const T (&x)[D], int cls)
+{
+    if (p->mode == 0) return cls == kGoal ? p->g_goal : (cls == kOuter ? p->g_outer : p->g_obs);
+    T xb[D];
+    closest_point<T, D>(p, x, cls, xb);
+    T s = 0;
+#pragma unroll
+    for (int i = 0; i < D; ++i) s = Math<T>::fma(p->ak[i], xb[i], s);
+    return p->mode == 1 ? s + p->b : Math<T>::exp(s);
+}
+
+// 0F1(; b; y) by Horner's rule on the host-computed coefficients.
+template <typename T, typename C>
+__device__ __forceinline__ T horner(const C& c, int nt, T y)
+{
+    T acc = c[nt - 1];
+    for (int i = nt - 2; i >= 0; --i) acc = Math<T>::fma(acc, y, c[i]);
+    return acc;
+}
+
+// ------------------------------------------------------------------------
+// One walk (Sec. IV-A).  State lives in registers; an iteration makes one
+// distance evaluation and either absorbs (eps-shell, Fig. 2) or applies the
+// step's weight and jumps to a uniform point on the sphere of radius R.
+// ------------------------------------------------------------------------
+template <typename T, int D>
+struct Walker {
+    T x[D];    // current point x_k
+    T v0[D];   // first direction
+    T W;       // prod_{i < k} C(R_i): weight of u_hat(x_0)
+    T W1;      // prod_{1 <= i < k} C(R_i): weight of u_hat(x_1)
+    T gfac;    // (d / R_0) C1(R_0)
+    T S;       // sum_{i < k} d ln C(R_i) / d sigma
+    uint32_t k;
+    uint32_t w;
+};
+
+template <typename T>
+struct WalkEnd {
+    T u;        // u_hat(x_0)
+    T gs;       // gradient = gs * v0
+    T S;        // d ln u_hat / d sigma
+    T goal_w;   // W 1{goal}
+    uint32_t steps;
+    int32_t status, cls;
+};
+
+template <typename T, int D, int DA>
+__device__ __forceinline__ void walker_start(Walker<T, DA>& s, const T (&xq)[DA], uint32_t w)
+{
+#pragma unroll
+    for (int i = 0; i < D; ++i) s.x[i] = xq[i];
+#pragma unroll
+    for (int i = 0; i < DA; ++i) s.v0[i] = T(0);
+    s.W = T(1);
+    s.W1 = T(1);
+    s.gfac = T(0);
+    s.S = T(0);
+    s.k = 0;
+    s.w = w;
+}
+
+// Returns true when the walk ended (e is then filled in).  (key0, key1) is
+// the Philox key of the launch, q the query's index in its environment.  The
+// walker may store DA >= D coordinates; only the first D are used.
+template <typename T, int D, bool BWD, int DA = D>
+__device__ __forceinline__ bool walker_step(cenv<T> p0, Walker<T, DA>& s, uint32_t q, uint32_t key0,
+                                            uint32_t key1, WalkEnd<T>& e)
+{
+    static_assert(DA >= D, "walker storage narrower than the dimension");
+    const T(&x)[D] = reinterpret_cast<const T(&)[D]>(s.x);
+    int cls;
+    const T R = distance<T, D>(fresh(p0), x, cls);
+    cenv<T> p = fresh(p0);
+    const uint32_t k = s.k;
+    if (R < p->eps) {
+        const T g = boundary_value<T, D>(p, x, cls);
+        const bool first = (k == 0);
+        e.steps = k + 1;
+        e.cls = cls;
+        e.status = first ? kDegenerate : kAbsorbed;
+        e.u = s.W * g;
+        e.gs = first ? T(0) : s.gfac * s.W1 * g;
+        e.S = s.S;
+        e.goal_w = (cls == kGoal) ? s.W : T(0);
+        return true;
+    }
+    if (k + 1 >= p->max_steps) {
+        e.steps = k + 1;
+        e.cls = cls;
+        e.status = kTruncated;
+        e.u = T(0);
+        e.gs = T(0);
+        e.S = T(0);
+        e.goal_w = T(0);
+        return true;
+    }
+    const T R2 = R * R;
+    const T y = p->qsigma * R2;
+    const T C = Math<T>::rcp(horner<T>(p->cC, p->nt_C, y));
+    p = fresh(p0);
+    s.W *= C;
+    s.W1 *= (k > 0) ? C : T(1);
+    if (BWD) {
+        const T p1 = horner<T>(p->cC1, p->nt_C1, y);
+        s.S = Math<T>::fma(T(-0.5 / D) * R2 * p1, C, s.S);
+        if (k == 0) s.gfac = (T(D) / R) * Math<T>::rcp(p1);
+    } else if (k == 0) {
+        s.gfac = (T(D) / R) * Math<T>::rcp(horner<T>(p->cC1, p->nt_C1, y));
+    }
+    T v[D];
+    direction<T, D>(k, s.w, q, fresh(p0)->env_id, key0, key1, v);
+    if (k == 0) {
+#pragma unroll
+        for (int i = 0; i < D; ++i) s.v0[i] = v[i];
+    }
+#pragma unroll
+    for (int i = 0; i < D; ++i) s.x[i] = Math<T>::fma(R, v[i], s.x[i]);
+    s.k = k + 1;
+    return false;
+}
+
+// ------------------------------------------------------------------------
+// Wave-level sums (64 lanes) of FP64 accumulators.
+// ------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+}  // namespace wos

@@ -1,0 +1,66 @@
+// wos_params.hpp -- parameter blocks shared by the host launcher and the walk
+// kernels of libwos (internal; not part of the C ABI).
+#pragma once
+#include <stdint.h>
+
+namespace wos {
+
+constexpr int kMaxDim = 8;
+constexpr int kMaxTerms = 96;      // Horner terms of the 0F1 weight series
+constexpr int kBatchStride = 8;    // row stride of batched query / gradient arrays
+constexpr int kWave = 64;          // CDNA wavefront width
+constexpr uint32_t kDefaultMaxSteps = 1u << 16;
+
+enum Class : int32_t { kGoal = 0, kSphere = 1, kBox = 2, kOuter = 3 };
+enum Status : int32_t { kAbsorbed = 0, kDegenerate = 1, kTruncated = 2 };
+
+// Row strides of the device obstacle tables (elements): a sphere row holds
+// centre[d], radius; a box row holds centre[d], half_width[d].  Rows are
+// padded to a multiple of 4 elements so scalar loads fetch whole rows.
+__host__ __device__ constexpr int sph_stride(int d) { return ((d + 1 + 3) / 4) * 4; }
+__host__ __device__ constexpr int box_stride(int d) { return ((2 * d + 3) / 4) * 4; }
+
+// Per-environment parameters of one walk launch.  Read by every lane with
+// wave-uniform addresses, so the compiler keeps them in scalar registers.
+template <typename T>
+struct EnvP {
+    const T* sph;          // n_sph x sph_stride(d)
+    const T* box;          // n_box x box_stride(d)
+    int32_t n_sph, n_box;
+    int32_t d, has_goal;
+    int32_t outer_kind, mode;  // outer: 0 box, 1 ball; mode: 0 class, 1 affine, 2 plane
+    int32_t nt_C, nt_C1;       // Horner terms of 0F1(;d/2;y) and 0F1(;d/2+1;y)
+    uint32_t key0, key1;       // Philox key (seed)
+    uint32_t env_id, max_steps;
+    T goal_c[kMaxDim];
+    T goal_r;
+    T lo[kMaxDim], hi[kMaxDim];
+    T oc[kMaxDim];
+    T orad;
+    T g_goal, g_obs, g_outer, b;
+    T ak[kMaxDim];
+    T sigma, eps, qsigma;      // qsigma = sigma / 4
+    T cC[kMaxTerms];           // c_k = 1 / ((d/2)_k k!)
+    T cC1[kMaxTerms];          // c_k = 1 / ((d/2 + 1)_k k!)
+};
+
+// Work decomposition of one environment inside a batched launch.
+struct BatchEnv {
+    int64_t q_off;      // first row of the env's queries in the batch arrays
+    int64_t unit_off;   // first work-unit index of the env
+    int64_t n_walks;    // walks per query of the env
+    int32_t n_q;        // queries of the env
+    int32_t splits;     // work units per query (walk ranges)
+    int32_t wps;        // walks per work unit (last unit may be shorter)
+    int32_t d;
+    int32_t q_stride;   // row stride of the query array (elements)
+    int32_t slot;       // position of the env in the caller's env array
+};
+
+// Accumulator layout of one work unit's partial sums (doubles):
+// [0] sum u, [1] sum u^2, [2, 2+d) sum grad, [2+d, 2+2d) sum grad^2,
+// [2+2d] sum steps, [3+2d] truncated, [4+2d] degenerate,
+// [5+2d] sum u*S (d u/d sigma), [6+2d] sum W 1{goal} (d u/d g_goal).
+__host__ __device__ constexpr int nacc(int d) { return 7 + 2 * d; }
+
+}  // namespace wos

@@ -220,14 +220,18 @@ def scene_c3(n_walks=16384, seed=0, n_seg=32, per_seg=32):
     return s
 
 
-def scene_c4_env(e, n_walks=2048, seed=0, q_cap=None):
+def scene_c4_env(e, n_walks=2048, seed=0, q_cap=None, dims=None):
     """Environment ``e`` of the ragged batch (rng seed e): d ~ U{2..7},
     M = round(exp(U[ln 16, ln 2048])) spheres r U[0.05, 0.4],
     Q = round(exp(U[0, ln 4096])) queries, sigma ~ U[0.5, 8], eps = 1e-4,
     goal r = 0.15 (0.1 for d = 2).  Queries are uniform free points; a query
-    that stays unclear for 64 draws is kept (packed low-d scenes)."""
+    that stays unclear for 64 draws is kept (packed low-d scenes).  With
+    ``dims`` given, an environment of another dimension is not drawn further
+    and None is returned (every environment has its own generator)."""
     rng = np.random.default_rng(e)
     d = int(rng.integers(2, 8))
+    if dims is not None and d not in dims:
+        return None
     m = int(round(math.exp(rng.uniform(math.log(16), math.log(2048)))))
     q = int(round(math.exp(rng.uniform(0.0, math.log(4096)))))
     sigma = float(rng.uniform(0.5, 8.0))
@@ -251,8 +255,8 @@ def scene_c4(n_envs=512, n_walks=2048, seed=0, dims=None, q_cap=None):
     dimension is in ``dims``."""
     envs = []
     for e in range(n_envs):
-        s = scene_c4_env(e, n_walks, seed, q_cap)
-        if dims is None or s["d"] in dims:
+        s = scene_c4_env(e, n_walks, seed, q_cap, dims)
+        if s is not None:
             s["env_id"] = e
             envs.append(s)
     return envs

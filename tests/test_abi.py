@@ -1,0 +1,113 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every function include/wos.h declares, and rejects bad arguments before it
+touches the device."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "wos.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(wos_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_2406_01713_amd import binding
+    return binding
+
+
+def test_header_declares_the_paper_calls():
+    names = declared_functions()
+    for f in ["wos_create_domain", "wos_estimate", "wos_backward", "wos_estimate_batch",
+              "wos_plan_create", "wos_plan_step", "wos_autotune", "wos_last_error"]:
+        assert f in names
+
+
+def test_library_exports_every_declared_symbol(B):
+    names = declared_functions()
+    missing = [n for n in names if not hasattr(B.lib, n)]
+    assert not missing, missing
+    assert sorted(B.EXPORTED) == names
+
+
+def _bdata(B):
+    return B.BData(0, 1.0, 0.0, 0.0, None, 0.0)
+
+
+def _outer(B, d):
+    lo = np.full(d, -1.0)
+    hi = np.full(d, 1.0)
+    return B.Outer(B.WOS_OUTER_BOX, lo.ctypes.data_as(C.POINTER(C.c_double)),
+                   hi.ctypes.data_as(C.POINTER(C.c_double)), None, 0.0), (lo, hi)
+
+
+def test_create_domain_rejects_bad_dimension(B):
+    h = C.c_void_p()
+    o, keep = _outer(B, 8)
+    bd = _bdata(B)
+    for d in (0, 1, 9, 100):
+        rc = B.lib.wos_create_domain(d, None, None, None, C.byref(o), C.byref(bd), C.byref(h))
+        assert rc == B.WOS_EDIM
+        assert b"outside" in B.lib.wos_last_error()
+    assert B.lib.wos_create_domain(3, None, None, None, None, C.byref(bd), C.byref(h)) == B.WOS_EINVAL
+    assert B.lib.wos_create_domain(3, None, None, None, C.byref(o), None, C.byref(h)) == B.WOS_EINVAL
+    assert B.lib.wos_create_domain(3, None, None, None, C.byref(o), C.byref(bd), None) == B.WOS_EINVAL
+
+
+def test_create_domain_rejects_bad_obstacles(B):
+    d = 2
+    h = C.c_void_p()
+    o, keep = _outer(B, d)
+    bd = _bdata(B)
+    c = np.zeros((1, d))
+    r = np.array([-0.5])
+    sp = B.Spheres(1, c.ctypes.data_as(C.POINTER(C.c_double)), r.ctypes.data_as(C.POINTER(C.c_double)))
+    assert B.lib.wos_create_domain(d, C.byref(sp), None, None, C.byref(o), C.byref(bd), C.byref(h)) == B.WOS_EINVAL
+    r2 = np.array([np.nan])
+    sp2 = B.Spheres(1, c.ctypes.data_as(C.POINTER(C.c_double)), r2.ctypes.data_as(C.POINTER(C.c_double)))
+    assert B.lib.wos_create_domain(d, C.byref(sp2), None, None, C.byref(o), C.byref(bd), C.byref(h)) == B.WOS_EINVAL
+    sp3 = B.Spheres(1, None, None)
+    assert B.lib.wos_create_domain(d, C.byref(sp3), None, None, C.byref(o), C.byref(bd), C.byref(h)) == B.WOS_EINVAL
+    bad = B.BData(7, 1.0, 0.0, 0.0, None, 0.0)
+    assert B.lib.wos_create_domain(d, None, None, None, C.byref(o), C.byref(bad), C.byref(h)) == B.WOS_EINVAL
+    lo = np.array([1.0, -1.0])
+    hi = np.array([-1.0, 1.0])
+    ob = B.Outer(B.WOS_OUTER_BOX, lo.ctypes.data_as(C.POINTER(C.c_double)),
+                 hi.ctypes.data_as(C.POINTER(C.c_double)), None, 0.0)
+    assert B.lib.wos_create_domain(d, None, None, None, C.byref(ob), C.byref(bd), C.byref(h)) == B.WOS_EINVAL
+
+
+def test_calls_reject_null_handles(B):
+    assert B.lib.wos_estimate(None, None, 1, 16, 1.0, 1e-3, 0, None, None, None, None, None) == B.WOS_EINVAL
+    assert B.lib.wos_backward(None, None, 1, 16, 1.0, 1e-3, 0, None, None, None, None, None, None,
+                              None) == B.WOS_EINVAL
+    assert B.lib.wos_plan_step(None, 1) == B.WOS_EINVAL
+    assert B.lib.wos_domain_dim(None) == B.WOS_EINVAL
+    assert B.lib.wos_autotune(1, 10, 10, 64, b"/tmp/x.json") == B.WOS_EDIM
+    assert B.lib.wos_estimate_batch(None, 0, None, None, None, None, None, 0, None, None, None, None,
+                                    None, None, None, None, None) == B.WOS_OK
+    opt = B.Options(B.WOS_FP64, 0, 0, 0)
+    assert B.lib.wos_estimate_batch(None, 1, None, None, None, None, None, 0, None, None, None, None,
+                                    None, None, None, C.byref(opt), None) == B.WOS_ENOTSUP
+    B.lib.wos_destroy_domain(None)
+    B.lib.wos_plan_destroy(None)
+
+
+def test_product_path_imports_no_oracle():
+    """The library package never imports, links or runs the oracle."""
+    pkg = os.path.join(ROOT, "paper_2406_01713_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".cpp", ".hip", ".hpp", ".h")):
+                src = open(os.path.join(dirpath, f)).read()
+                for pat in (r"^\s*(from|import)\s+oracle\b", r"wos_oracle", r"libwos_oracle",
+                            r"#include\s+[<\"].*oracle"):
+                    assert not re.search(pat, src, flags=re.M), (f, pat)

@@ -1,0 +1,441 @@
+"""GPU parity: the HIP path, called through the C ABI, against the FP64 CPU
+oracle on identical Philox streams.  Bar: per query |u_gpu - u_cpu| <= 4 SE_cpu
++ 1e-7 (same for each gradient component); walk-level agreement where the
+walks coincide; FP32 bias against the closed-form ball solution < 1e-3
+relative; batched and plain paths agree up to summation order."""
+import math
+import os
+import tempfile
+
+import numpy as np
+import pytest
+
+from paper_2406_01713_amd import scenes as S
+from tests.pins import closed_forms as CF
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2406_01713_amd import binding
+    return binding
+
+
+def dev(a, dtype):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+def gpu_estimate(B, scene, fp64=False, queries=None, n_walks=None, seed=None, env_id=0,
+                 max_steps=0, sigma=None, eps=None):
+    import torch
+    dt = torch.float64 if fp64 else torch.float32
+    dom = B.Domain(scene)
+    q = dev(scene["queries"] if queries is None else queries, dt)
+    Q, d = q.shape
+    u = torch.empty(Q, dtype=dt, device="cuda")
+    g = torch.empty(Q, d, dtype=dt, device="cuda")
+    st = torch.empty(Q, d + 4, dtype=torch.float64, device="cuda")
+    B.wos_estimate(dom, q, scene["n_walks"] if n_walks is None else n_walks,
+                   scene["sigma"] if sigma is None else sigma, scene["eps"] if eps is None else eps,
+                   scene["seed"] if seed is None else seed, u, g, st,
+                   opt=B.options(fp64, env_id, max_steps))
+    torch.cuda.synchronize()
+    return u.cpu().numpy().astype(np.float64), g.cpu().numpy().astype(np.float64), st.cpu().numpy()
+
+
+def gpu_backward(B, scene, ubar, fp64=False, queries=None, n_walks=None, seed=None, env_id=0):
+    import torch
+    dt = torch.float64 if fp64 else torch.float32
+    dom = B.Domain(scene)
+    q = dev(scene["queries"] if queries is None else queries, dt)
+    Q, d = q.shape
+    dx = torch.empty(Q, d, dtype=dt, device="cuda")
+    ds = torch.empty(1, dtype=torch.float64, device="cuda")
+    dg = torch.empty(1, dtype=torch.float64, device="cuda")
+    dq = torch.empty(Q, 2, dtype=torch.float64, device="cuda")
+    B.wos_backward(dom, q, scene["n_walks"] if n_walks is None else n_walks, scene["sigma"],
+                   scene["eps"], scene["seed"] if seed is None else seed, dev(ubar, dt), dx, ds, dg,
+                   dq, opt=B.options(fp64, env_id))
+    torch.cuda.synchronize()
+    return dx.cpu().numpy().astype(np.float64), float(ds.item()), float(dg.item()), dq.cpu().numpy()
+
+
+def assert_within_4se(u_gpu, g_gpu, u_cpu, g_cpu, st_cpu, d, extra=0.0):
+    tol_u = 4 * st_cpu[:, 0] + 1e-7 + extra
+    bad = np.abs(u_gpu - u_cpu) > tol_u
+    assert not bad.any(), (np.nonzero(bad)[0], u_gpu[bad], u_cpu[bad], tol_u[bad])
+    tol_g = 4 * st_cpu[:, 1:1 + d] + 1e-7 + extra
+    badg = np.abs(g_gpu - g_cpu) > tol_g
+    assert not badg.any(), (np.argwhere(badg)[:5], g_gpu[badg][:5], g_cpu[badg][:5])
+
+
+def subset(name, nq, nw, seed=0):
+    if name == "c1":
+        s = S.scene_c1(n_walks=nw, seed=seed)
+        s["queries"] = s["queries"][:nq]
+    elif name == "c2":
+        s = S.scene_c2(n_queries=nq, n_walks=nw, seed=seed)
+    elif name == "c3":
+        s = S.scene_c3(n_walks=nw, seed=seed)
+        s["queries"] = s["queries"][::max(1, 1024 // nq)][:nq]
+    else:
+        s = S.scene_c5(n_starts=nq, n_walks=nw, seed=seed)
+    return s
+
+
+# --------------------------------------------------------------- walks ----
+
+@pytest.mark.parametrize("fp64", [True, False])
+@pytest.mark.parametrize("name", ["c1", "c3", "c5"])
+def test_walk_level_parity(B, oracle, name, fp64):
+    """Same Philox counters -> same walks: step counts agree for almost every
+    walk; where they agree the one-point estimates agree to rounding."""
+    s = subset(name, 2, 128, seed=11)
+    dom = B.Domain(s)
+    odom = oracle.Domain(s)
+    n = 128
+    for qi, x in enumerate(s["queries"]):
+        rec = B.wos_debug_walks(dom, x, qi, 0, n, s["sigma"], s["eps"], s["seed"], B.options(fp64))
+        d = s["d"]
+        same = 0
+        for w in range(n):
+            r = oracle.walk(s, x, w, qi, dom=odom)
+            gsteps = int(rec[w, d + 3])
+            if gsteps != r["steps"]:
+                continue
+            same += 1
+            tol = 1e-9 if fp64 else 2e-4
+            assert abs(rec[w, 0] - r["u"]) <= tol * max(1.0, abs(r["u"])), (w, rec[w, 0], r["u"])
+            assert np.allclose(rec[w, 1:1 + d], r["grad"], rtol=tol * 10, atol=tol * 10 * max(1.0, np.abs(r["grad"]).max()))
+            assert int(rec[w, d + 4]) == r["status"]
+            if r["status"] != 2:
+                assert int(rec[w, d + 5]) == r["cls"]
+            assert abs(rec[w, d + 2] - r["goal_w"]) <= tol * max(1.0, abs(r["goal_w"]))
+        frac = same / n
+        assert frac >= (0.97 if fp64 else 0.80), frac
+
+
+# ------------------------------------------------------------- queries ----
+
+def test_rr_config_fp64_full(B, oracle):
+    """The d = 2 RR configuration at full size (64 grid queries x 1024 walks,
+    FP64 plain kernel)."""
+    s = S.scene_c1()
+    u, g, st = gpu_estimate(B, s, fp64=True)
+    uc, gc, stc = oracle.estimate(s)
+    assert_within_4se(u, g, uc, gc, stc, 2)
+    assert np.array_equal(st[:, 2 + 3], stc[:, 2 + 3])  # degenerate counts
+    assert np.allclose(st[:, 0], stc[:, 0], rtol=0.05, atol=1e-9)
+
+
+@pytest.mark.parametrize("name,nq,nw", [("c1", 16, 2048), ("c2", 24, 1024), ("c3", 16, 1024),
+                                        ("c5", 6, 512)])
+def test_fp32_plain_vs_oracle(B, oracle, name, nq, nw):
+    s = subset(name, nq, nw, seed=3)
+    u, g, st = gpu_estimate(B, s)
+    uc, gc, stc = oracle.estimate(s)
+    assert_within_4se(u, g, uc, gc, stc, s["d"])
+    assert np.allclose(st[:, s["d"] + 1], stc[:, s["d"] + 1], rtol=0.05)  # mean walk length
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("name", ["c3", "c5"])
+def test_fp32_affine_and_plane_wave_vs_oracle(B, oracle, name, mode):
+    s = subset(name, 6, 1024, seed=5)
+    d = s["d"]
+    if mode == 1:
+        s = S.with_bdata(s, 1, ak=np.linspace(-1, 1, d), b=0.3)
+        s["sigma"] = 0.0
+    else:
+        s = S.with_bdata(s, 2, ak=S.plane_wave_k(d, s["sigma"], seed=4))
+    u, g, st = gpu_estimate(B, s)
+    uc, gc, stc = oracle.estimate(s)
+    scale = np.maximum(1.0, np.abs(uc))
+    assert_within_4se(u, g, uc, gc, stc, d, extra=2e-5 * scale[:, None].max())
+
+
+@pytest.mark.parametrize("d", [2, 5, 7])
+def test_fp32_bias_vs_ball_closed_form(B, d):
+    """FP32 walks, 2^22 per point: |u - u_exact| < 1e-3 u_exact."""
+    sigma = 2.0
+    pts = np.zeros((2, d))
+    pts[0, 0] = 0.5
+    pts[1, d - 1] = -0.3
+    pts[1, 0] = 0.2
+    s = S.scene_ball(d, R=1.0, sigma=sigma, eps=1e-4, queries=pts, n_walks=1 << 22, seed=17)
+    u, g, st = gpu_estimate(B, s)
+    for q, x in enumerate(pts):
+        ue = CF.ball_u(d, sigma, 1.0, x)
+        assert abs(u[q] - ue) < 1e-3 * ue, (q, u[q], ue, st[q, 0])
+        assert abs(u[q] - ue) <= 4 * st[q, 0] + 2e-4 * ue
+        ge = CF.ball_grad(d, sigma, 1.0, x)
+        assert np.all(np.abs(g[q] - ge) <= 4 * st[q, 1:1 + d] + 1e-3 * np.linalg.norm(ge))
+
+
+def test_fp64_gpu_ball_centre_exact(B):
+    from tests.test_oracle_rng_series import _C_bessel
+    for d in (3, 7):
+        s = S.scene_ball(d, R=1.3, sigma=3.0, n_walks=4096)
+        u, g, st = gpu_estimate(B, s, fp64=True)
+        assert u[0] == pytest.approx(_C_bessel(d, 3.0, 1.3), rel=1e-12)
+        assert st[0, 0] < 1e-14 and st[0, d + 1] == 2.0
+
+
+# ------------------------------------------------------------ backward ----
+
+def test_backward_vs_oracle_fp64(B, oracle):
+    s = subset("c3", 6, 512, seed=8)
+    rng = np.random.default_rng(0)
+    ubar = rng.normal(size=6)
+    dx, ds, dg, dq = gpu_backward(B, s, ubar, fp64=True)
+    dxc, dsc, dgc = oracle.backward(s, ubar)
+    _, _, stc, dqc = oracle.estimate(s, dq=True)
+    d = s["d"]
+    assert np.all(np.abs(dx - dxc) <= 4 * np.abs(ubar)[:, None] * stc[:, 1:1 + d] + 1e-9)
+    # per walk S and goal weights coincide with the oracle's on matching walks,
+    # so the per-query sensitivities agree to rounding unless a walk flipped
+    assert np.allclose(dq, dqc, rtol=2e-3, atol=1e-9)
+    assert ds == pytest.approx(dsc, rel=5e-3, abs=1e-9)
+    assert dg == pytest.approx(dgc, rel=5e-3, abs=1e-9)
+
+
+def test_backward_matches_crn_finite_differences_fp64(B):
+    s = subset("c3", 4, 1024, seed=9)
+    ubar = np.ones(4)
+    _, _, _, dq = gpu_backward(B, s, ubar, fp64=True)
+    h = 1e-4
+    up = gpu_estimate(B, s, fp64=True, sigma=s["sigma"] + h)[0]
+    um = gpu_estimate(B, s, fp64=True, sigma=s["sigma"] - h)[0]
+    assert np.allclose(dq[:, 0], (up - um) / (2 * h), rtol=1e-5, atol=1e-10)
+    s1 = dict(s, bdata=dict(s["bdata"], g_goal=3.0))
+    u1 = gpu_estimate(B, s1, fp64=True)[0]
+    u0 = gpu_estimate(B, s, fp64=True)[0]
+    assert np.allclose(dq[:, 1], (u1 - u0) / 2.0, rtol=1e-10, atol=1e-14)
+
+
+def test_backward_vs_ball_closed_form(B):
+    d, sigma = 5, 2.0
+    x = np.zeros((1, d))
+    x[0, 1] = 0.4
+    s = S.scene_ball(d, R=1.0, sigma=sigma, eps=1e-4, queries=x, n_walks=1 << 20, seed=2)
+    dx, ds, dg, dq = gpu_backward(B, s, np.ones(1))
+    want = CF.ball_du_dsigma(d, sigma, 1.0, x[0])
+    assert dq[0, 0] == pytest.approx(want, rel=1e-2)
+    _, _, st = gpu_estimate(B, s)  # same walks: their gradient standard errors
+    ge = CF.ball_grad(d, sigma, 1.0, x[0])
+    assert np.all(np.abs(dx[0] - ge) <= 4 * st[0, 1:1 + d] + 1e-4), (dx[0], ge, st[0, 1:1 + d])
+
+
+def test_autograd_function(B):
+    import torch
+    from paper_2406_01713_amd.autograd import WoSFunction
+    s = subset("c3", 8, 512, seed=1)
+    x = dev(s["queries"], torch.float64).requires_grad_(True)
+    sig = torch.tensor(s["sigma"], dtype=torch.float64, requires_grad=True)
+    gg = torch.tensor(1.0, dtype=torch.float64, requires_grad=True)
+    u, g = WoSFunction.apply(x, sig, gg, s, s["n_walks"], s["eps"], s["seed"])
+    w = torch.linspace(-1, 1, 8, dtype=torch.float64, device="cuda")
+    (u * w).sum().backward()
+    dx, ds, dgv, _ = gpu_backward(B, s, w.cpu().numpy(), fp64=True)
+    assert np.allclose(x.grad.cpu().numpy(), dx, rtol=1e-12, atol=1e-15)
+    assert sig.grad.item() == pytest.approx(ds, rel=1e-12)
+    assert gg.grad.item() == pytest.approx(dgv, rel=1e-12)
+    assert np.allclose(g.detach().cpu().numpy(), gpu_estimate(B, s, fp64=True)[1], rtol=1e-12)
+
+
+# --------------------------------------------------------------- batch ----
+
+def _ragged(n_envs=10, q_cap=24, n_walks=512):
+    envs = [S.scene_c4_env(e, n_walks=n_walks, seed=7, q_cap=q_cap) for e in range(n_envs)]
+    return envs
+
+
+def gpu_batch(B, envs, n_walks, seed, ubar=None, torch_dtype=None):
+    import torch
+    doms = [B.Domain(e) for e in envs]
+    Qs = [len(e["queries"]) for e in envs]
+    off = np.concatenate([[0], np.cumsum(Qs)]).astype(np.int64)
+    qp = np.zeros((off[-1], 8), dtype=np.float32)
+    for e, s in enumerate(envs):
+        qp[off[e]:off[e + 1], :s["d"]] = s["queries"]
+    q = dev(qp, torch.float32)
+    n = int(off[-1])
+    u = torch.empty(n, device="cuda")
+    g = torch.empty(n, 8, device="cuda")
+    st = torch.empty(n, 12, dtype=torch.float64, device="cuda")
+    kw = {}
+    if ubar is not None:
+        kw = dict(grad_u=dev(ubar, torch.float32), out_dx=torch.empty(n, 8, device="cuda"),
+                  out_dsigma=torch.empty(len(envs), dtype=torch.float64, device="cuda"),
+                  out_dg=torch.empty(len(envs), dtype=torch.float64, device="cuda"))
+    B.wos_estimate_batch(doms, q, off, [e["sigma"] for e in envs], [e["eps"] for e in envs], n_walks,
+                         seed, u, g, st, **kw)
+    torch.cuda.synchronize()
+    out = {"u": u.cpu().numpy(), "g": g.cpu().numpy(), "st": st.cpu().numpy(), "off": off}
+    if ubar is not None:
+        out.update(dx=kw["out_dx"].cpu().numpy(), ds=kw["out_dsigma"].cpu().numpy(),
+                   dg=kw["out_dg"].cpu().numpy())
+    return out
+
+
+def test_batch_matches_plain_per_env(B):
+    """One persistent fused launch over a ragged batch (d in 2..7, uneven M and
+    Q) reproduces per-env plain forward and backward calls with env_id = e."""
+    envs = _ragged()
+    n_walks, seed = 512, 7
+    rng = np.random.default_rng(3)
+    Qt = sum(len(e["queries"]) for e in envs)
+    ubar = rng.normal(size=Qt).astype(np.float32)
+    out = gpu_batch(B, envs, n_walks, seed, ubar=ubar)
+    off = out["off"]
+    for e, s in enumerate(envs):
+        d = s["d"]
+        sl = slice(off[e], off[e + 1])
+        u, g, st = gpu_estimate(B, s, n_walks=n_walks, seed=seed, env_id=e)
+        assert np.allclose(out["u"][sl], u, rtol=2e-5, atol=1e-7), e
+        assert np.allclose(out["g"][sl, :d], g, rtol=2e-5, atol=1e-6), e
+        assert np.all(out["g"][sl, d:] == 0)
+        assert np.allclose(out["st"][sl, 9], st[:, d + 1], rtol=1e-12)  # mean steps: identical walks
+        assert np.array_equal(out["st"][sl, 11], st[:, d + 3])
+        dx, ds, dg, dq = gpu_backward(B, s, ubar[sl], n_walks=n_walks, seed=seed, env_id=e)
+        assert np.allclose(out["dx"][sl, :d], dx, rtol=2e-5, atol=1e-6), e
+        assert out["ds"][e] == pytest.approx(ds, rel=1e-4, abs=1e-8)
+        assert out["dg"][e] == pytest.approx(dg, rel=1e-4, abs=1e-8)
+
+
+def test_batch_vs_oracle(B, oracle):
+    envs = _ragged(n_envs=6, q_cap=4, n_walks=256)
+    out = gpu_batch(B, envs, 256, 7)
+    for e, s in enumerate(envs):
+        sl = slice(out["off"][e], out["off"][e + 1])
+        uc, gc, stc = oracle.estimate(s, n_walks=256, seed=7, env=e)
+        assert_within_4se(out["u"][sl].astype(np.float64), out["g"][sl, :s["d"]].astype(np.float64),
+                          uc, gc, stc, s["d"])
+
+
+def test_batch_is_deterministic(B):
+    envs = _ragged(n_envs=5, q_cap=16, n_walks=256)
+    a = gpu_batch(B, envs, 256, 3, ubar=np.ones(sum(len(e["queries"]) for e in envs), np.float32))
+    b = gpu_batch(B, envs, 256, 3, ubar=np.ones(sum(len(e["queries"]) for e in envs), np.float32))
+    for k in ("u", "g", "st", "dx", "ds", "dg"):
+        assert np.array_equal(a[k], b[k]), k
+
+
+def test_autotune_writes_cache_and_batch_uses_it(B):
+    with tempfile.TemporaryDirectory() as td:
+        path = os.path.join(td, "tune.json")
+        B.wos_autotune(7, 64, 32, 256, path)
+        txt = open(path).read()
+        assert "units_per_wave" in txt and "d7_" in txt
+        B.wos_set_autotune_cache(path)
+        envs = _ragged(n_envs=3, q_cap=8, n_walks=256)
+        a = gpu_batch(B, envs, 256, 5)
+        B.wos_set_autotune_cache(None)
+        b = gpu_batch(B, envs, 256, 5)
+        assert np.allclose(a["u"], b["u"], rtol=2e-5, atol=1e-7)
+
+
+# ------------------------------------------------------------ planning ----
+
+def test_plan_graph_matches_oracle_steps(B, oracle):
+    import torch
+    s = S.scene_c5(n_starts=3, n_walks=512)
+    rng = np.random.default_rng(3)
+    starts = []
+    while len(starts) < 4:
+        v = rng.normal(size=7)
+        p = s["goal_c"] + (s["goal_r"] + 0.1) * v / np.linalg.norm(v)
+        if S.is_clear(p, s, 0.05):
+            starts.append(p)
+    x0 = np.array(starts)
+    x = dev(x0, torch.float32)
+    dom = B.Domain(s)
+    plan = B.Plan(dom, x, 512, s["sigma"], s["eps"], s["s_ub"], s["seed"])
+    xo = np.ascontiguousarray(x0.astype(np.float32).astype(np.float64))
+    path = np.zeros(4)
+    stalls = np.zeros(4, dtype=np.int32)
+    status = np.zeros(4, dtype=np.int32)
+    for t in range(3):
+        plan.step(1)
+        u, g, pl, stl, sts, step = plan.read()
+        oracle.plan_step(s, xo, t, path, stalls, status)
+        xg = x.cpu().numpy().astype(np.float64)
+        assert step[0] == t + 1
+        assert np.array_equal(stl, stalls) and np.array_equal(sts, status)
+        assert np.allclose(xg, xo, atol=2e-4), (t, np.abs(xg - xo).max())
+        assert np.allclose(pl, path, rtol=1e-4, atol=1e-6)
+    del plan
+
+
+# ---------------------------------------------------------- edge cases ----
+
+def test_edge_cases(B, oracle):
+    import torch
+    s = subset("c1", 4, 100, seed=2)  # 100 walks: a ragged 64-walk chunk
+    u, g, st = gpu_estimate(B, s, fp64=True)
+    uc, gc, stc = oracle.estimate(s)
+    assert_within_4se(u, g, uc, gc, stc, 2)
+    # one walk per query: SE = 0 and the value is that walk's
+    u1, _, st1 = gpu_estimate(B, s, fp64=True, n_walks=1)
+    assert np.all(st1[:, 0] == 0)
+    for q, x in enumerate(s["queries"]):
+        assert u1[q] == pytest.approx(oracle.walk(s, x, 0, q)["u"], rel=1e-9, abs=1e-12)
+    # degenerate queries: inside an obstacle, inside the goal, outside the box
+    c = S.scene_c1(n_walks=64)
+    qs = np.array([c["sph_c"][0], c["goal_c"], [4.0, 0.0]])
+    u, g, st = gpu_estimate(B, c, fp64=True, queries=qs)
+    assert u[0] == 0.0 and u[1] == 1.0 and u[2] == 0.0 and np.all(g == 0)
+    assert np.all(st[:, 2 + 3] == 64) and np.all(st[:, 2 + 1] == 1.0)
+    # truncation with a tiny step cap matches the oracle's count
+    u, g, st = gpu_estimate(B, s, fp64=True, max_steps=3)
+    uc, gc, stc = oracle.estimate(s, max_steps=3)
+    assert np.array_equal(st[:, 2 + 2], stc[:, 2 + 2])
+    # no queries: nothing launched, no error
+    dom = B.Domain(s)
+    q0 = torch.empty(0, 2, device="cuda")
+    B.wos_estimate(dom, q0, 64, 1.0, 1e-3, 0, torch.empty(0, device="cuda"))
+    # invalid arguments come back as errors
+    with pytest.raises(B.WosError):
+        B.wos_estimate(dom, dev(s["queries"], torch.float32), 0, 1.0, 1e-3, 0,
+                       torch.empty(4, device="cuda"))
+    with pytest.raises(B.WosError):
+        B.wos_estimate(dom, dev(s["queries"], torch.float32), 64, -1.0, 1e-3, 0,
+                       torch.empty(4, device="cuda"))
+    with pytest.raises(B.WosError):
+        B.wos_estimate(dom, dev(s["queries"], torch.float32), 64, 1.0, 0.0, 0,
+                       torch.empty(4, device="cuda"))
+    aff = B.Domain(S.with_bdata(s, 1, ak=[1.0, 0.0]))
+    with pytest.raises(B.WosError):
+        B.wos_estimate(aff, dev(s["queries"], torch.float32), 64, 1.0, 1e-3, 0,
+                       torch.empty(4, device="cuda"))
+
+
+# -------------------------------------------- full-size sampled parity ----
+
+@pytest.mark.parametrize("fused", [False, True])
+def test_d6_forward_full_size_sampled(B, oracle, fused):
+    """4096 queries x 4096 walks (d = 6): the full launch, checked on sampled
+    queries that the oracle recomputes one by one."""
+    s = S.scene_c2()
+    if fused:
+        out = gpu_batch(B, [s], s["n_walks"], s["seed"])
+        u, g = out["u"].astype(np.float64), out["g"][:, :6].astype(np.float64)
+        env = 0
+    else:
+        u, g, _ = gpu_estimate(B, s)
+        env = 0
+    idx = [0, 1777, 4095]
+    for q in idx:
+        # the oracle keys walks by the query's index: evaluate row q alone
+        dom = oracle.Domain(s)
+        vals = [oracle.walk(s, s["queries"][q], w, q, env=env, dom=dom) for w in range(s["n_walks"])]
+        uw = np.array([v["u"] for v in vals])
+        gw = np.array([v["grad"] for v in vals])
+        se_u = uw.std(ddof=1) / math.sqrt(len(uw))
+        se_g = gw.std(axis=0, ddof=1) / math.sqrt(len(uw))
+        assert abs(u[q] - uw.mean()) <= 4 * se_u + 1e-7
+        assert np.all(np.abs(g[q] - gw.mean(0)) <= 4 * se_g + 1e-7)
