@@ -277,6 +277,16 @@ int wos_debug_walks(const wos_domain* dom, const double* query, uint32_t q_index
                     int64_t n, double sigma, double eps, uint64_t seed, const wos_options* opt,
                     double* out_records);
 
+/*
+ * wos_microbench -- issue-rate microbenchmark on the current device, used as
+ * the measured roofline ceiling of the walk kernels.  which: 0 FP32 fused
+ * multiply-add (out_rate in FLOP/s, 2 per FMA), 1 FP32 square root
+ * (operations/s), 2 the 7-D sphere-distance loop of the walk kernels (sphere
+ * evaluations/s).  out_ms (nullable): kernel time.  Synchronous.
+ * Errors: WOS_EINVAL (bad which / NULL out_rate), WOS_EHIP.
+ */
+int wos_microbench(int which, double* out_rate, double* out_ms);
+
 /* wos_last_error -- message for the last failing call on this thread. */
 const char* wos_last_error(void);
 

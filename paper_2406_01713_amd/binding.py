@@ -26,7 +26,7 @@ MAX_DIM = 8
 EXPORTED = ["wos_create_domain", "wos_destroy_domain", "wos_domain_dim", "wos_estimate",
             "wos_backward", "wos_estimate_batch", "wos_plan_create", "wos_plan_step",
             "wos_plan_buffers", "wos_plan_read", "wos_plan_destroy", "wos_autotune", "wos_set_autotune_cache",
-            "wos_debug_walks", "wos_last_error"]
+            "wos_debug_walks", "wos_microbench", "wos_last_error"]
 
 
 class WosError(RuntimeError):
@@ -92,6 +92,7 @@ def _load():
     L.wos_set_autotune_cache.argtypes = [C.c_char_p]
     L.wos_debug_walks.argtypes = [vp, dp, u32, i64, i64, C.c_double, C.c_double, u64,
                                   C.POINTER(Options), dp]
+    L.wos_microbench.argtypes = [C.c_int, dp, dp]
     L.wos_last_error.restype = C.c_char_p
     return L
 
@@ -229,6 +230,14 @@ def wos_debug_walks(dom, query, q_index, w0, n, sigma, eps, seed, opt=None):
                               float(eps), int(seed), C.byref(opt) if opt is not None else None,
                               _dp(out)))
     return out
+
+
+def wos_microbench(which):
+    """(rate, ms): 0 FP32 FMA FLOP/s, 1 sqrt/s, 2 7-D sphere evaluations/s."""
+    r = C.c_double()
+    ms = C.c_double()
+    check(lib.wos_microbench(int(which), C.byref(r), C.byref(ms)))
+    return r.value, ms.value
 
 
 def wos_autotune(d, n_obstacles, n_queries, n_walks, cache_path):

@@ -19,8 +19,9 @@ LIB = os.path.join(PKG, "libwos.so")
 BUILD = os.path.join(ROOT, "_build")
 ARCH = os.environ.get("WOS_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["wos_kernels.hip", "wos_api.cpp"]
+SOURCES = ["wos_kernels.hip", "wos_api.cpp", "wos_microbench.hip"]
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-x", "hip",
+         *os.environ.get("WOS_EXTRA_FLAGS", "").split(),
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-function", "-I", os.path.join(ROOT, "include")]
 

@@ -114,16 +114,15 @@ __device__ __forceinline__ void philox4x32_10(uint32_t& c0, uint32_t& c1, uint32
 {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t lo0 = 0xD2511F53u * c0;
-        const uint32_t hi0 = __umulhi(0xD2511F53u, c0);
-        const uint32_t lo1 = 0xCD9E8D57u * c2;
-        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2);
-        const uint32_t y0 = hi1 ^ c1 ^ k0;
-        const uint32_t y2 = hi0 ^ c3 ^ k1;
+        // one 32x32->64-bit product per word (v_mad_u64_u32) gives both halves
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t y0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t y2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
         c0 = y0;
-        c1 = lo1;
+        c1 = (uint32_t)p1;
         c2 = y2;
-        c3 = lo0;
+        c3 = (uint32_t)p0;
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
     }
@@ -204,12 +203,16 @@ __device__ __forceinline__ T box_dist(const T (&x)[D], cptr<T> row)
     return Math<T>::sqrt(out2) + Math<T>::min(inside, T(0));
 }
 
+#ifndef WOS_SPHERE_UNROLL
+#define WOS_SPHERE_UNROLL 8
+#endif
+
 template <typename T, int D>
 __device__ __forceinline__ T spheres_min(cptr<T> sph, int n, const T (&x)[D])
 {
     constexpr int S = sph_stride(D);
     T best = Math<T>::inf();
-#pragma unroll 4
+#pragma unroll WOS_SPHERE_UNROLL
     for (int j = 0; j < n; ++j) best = Math<T>::min(best, sphere_dist<T, D>(x, sph + j * S));
     return best;
 }

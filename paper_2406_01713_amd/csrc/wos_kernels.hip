@@ -231,7 +231,9 @@ __device__ __forceinline__ bool step_any_d(int d, cenv<float> p, Walker<float, k
 
 // One work unit: walks [w_begin, w_end) of one query, with lane refill.  The
 // walker state and accumulator row are 8 wide for every d, so the dimension
-// only selects the step code.
+// only selects the step code.  (Keeping the accumulator row in LDS instead of
+// registers measured slower: its read-modify-write runs in every iteration in
+// which any lane of the wave finishes a walk, about half of them.)
 template <bool BWD>
 __device__ __forceinline__ void run_unit(cenv<float> p, CBatch& be, int64_t local, const float* queries,
                                          uint32_t k0, uint32_t k1, double* out)
@@ -286,8 +288,14 @@ __device__ __forceinline__ void run_unit(cenv<float> p, CBatch& be, int64_t loca
     wave_store<kNAccBatch>(a, out);
 }
 
+// 4 waves per SIMD: the register allocator then spills about 100 bytes per lane
+// of rarely used state, which measured faster than 3 waves without spills.
+#ifndef WOS_PERSISTENT_MIN_WAVES
+#define WOS_PERSISTENT_MIN_WAVES 4
+#endif
+
 template <bool BWD>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kBlock, WOS_PERSISTENT_MIN_WAVES)
 persistent_kernel(const EnvP<float>* envs, const BatchEnv* benv, int n_benv,
                   const float* __restrict__ queries, int64_t total_units,
                   uint32_t key0, uint32_t key1, const uint64_t* __restrict__ key_add,
