@@ -52,13 +52,28 @@ def kernel_hash():
 
 
 def distance_flops_per_step(s):
-    """Algorithmic FP32 operations of one distance evaluation: per sphere (and
-    the goal ball) d subtractions, d multiply-adds (2 flops), one subtraction
-    of the radius and one min: 3d + 2; per box 5d + 1; the outer box 4d."""
+    """FP32 operations of one distance evaluation that scans every obstacle:
+    per sphere (and the goal ball) d subtractions, d multiply-adds (2 flops),
+    one subtraction of the radius and one min: 3d + 2; per box 5d + 1; the
+    outer box 4d."""
     d = s["d"]
     ms = len(s["sph_r"]) + (1 if s.get("goal_r") is not None else 0)
     mb = len(s["box_h"])
     return ms * (3 * d + 2) + mb * (5 * d + 1) + 4 * d
+
+
+def executed_distance_flops(s, st):
+    """FP32 operations the distance evaluations of one env's walks actually
+    made, from the work columns of the batched stats (per-walk means of
+    sphere and box distances and cluster bounds evaluated): spheres, bounds
+    (same form as a sphere) and the goal 3d + 2 each, boxes 5d + 1, the outer
+    box 4d per step."""
+    d = s["d"]
+    steps = st[:, 9]
+    goal = 1.0 if s.get("goal_r") is not None else 0.0
+    per_walk = ((st[:, 12] + st[:, 14] + goal * steps) * (3 * d + 2) + st[:, 13] * (5 * d + 1)
+                + steps * 4 * d)
+    return float((per_walk * s["n_walks"]).sum())
 
 
 def workload():
@@ -128,9 +143,10 @@ def cpu_baseline(envs, budget_walks=400000):
 # ------------------------------------------------------------------ GPU ----
 
 class Batch:
-    def __init__(self, B, envs, torch, mode=0):
+    def __init__(self, B, envs, torch, mode=0, full_scan=False):
         from paper_2406_01713_amd import scenes as S
         self.B = B
+        self.opt = B.options(full_scan=full_scan)
         self.envs = envs
         if mode == 2:
             envs = [S.with_bdata(e, 2, ak=S.plane_wave_k(e["d"], e["sigma"], seed=i))
@@ -149,7 +165,7 @@ class Batch:
         self.eps = [e["eps"] for e in envs]
         self.u = torch.empty(n, device=dev)
         self.g = torch.empty(n, 8, device=dev)
-        self.st = torch.empty(n, 12, dtype=torch.float64, device=dev)
+        self.st = torch.empty(n, 15, dtype=torch.float64, device=dev)
         self.ubar = torch.ones(n, device=dev)
         self.dx = torch.empty(n, 8, device=dev)
         self.ds = torch.empty(len(envs), dtype=torch.float64, device=dev)
@@ -159,7 +175,7 @@ class Batch:
     def run(self, stats=True):
         self.B.wos_estimate_batch(self.doms, self.q, self.off, self.sig, self.eps, self.nw, self.seed,
                                   self.u, self.g, self.st if stats else None, self.ubar, self.dx,
-                                  self.ds, self.dg)
+                                  self.ds, self.dg, opt=self.opt)
 
 
 class Plain:
@@ -167,8 +183,9 @@ class Plain:
     kernels, one walk per lane), same walk identities as the batch.  Inputs
     and outputs are allocated before timing."""
 
-    def __init__(self, B, envs, doms, torch, seed):
+    def __init__(self, B, envs, doms, torch, seed, full_scan=False):
         self.B, self.envs, self.doms, self.seed = B, envs, doms, seed
+        self.full_scan = full_scan
         self.bufs = []
         for s in envs:
             q = torch.as_tensor(s["queries"], dtype=torch.float32, device="cuda")
@@ -183,7 +200,7 @@ class Plain:
         for e, (s, dom, b) in enumerate(zip(self.envs, self.doms, self.bufs)):
             if only is not None and e not in only:
                 continue
-            opt = B.options(False, e, 0)
+            opt = B.options(False, e, 0, full_scan=self.full_scan)
             B.wos_estimate(dom, b["q"], s["n_walks"], s["sigma"], s["eps"], self.seed, b["u"], b["g"], None,
                            opt=opt)
             B.wos_backward(dom, b["q"], s["n_walks"], s["sigma"], s["eps"], self.seed, b["ub"], b["dx"],
@@ -247,6 +264,8 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--full-scan", action="store_true",
+                    help="scan every obstacle each step (no cluster culling): same results, more work")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plan", action="store_true")
     ap.add_argument("--no-se", action="store_true")
@@ -277,7 +296,7 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     from paper_2406_01713_amd import binding as B
 
-    bat = Batch(B, envs, torch)
+    bat = Batch(B, envs, torch, full_scan=args.full_scan)
     st = torch.cuda.current_stream()
     if args.calib_copy_mib:
         n = args.calib_copy_mib * (1 << 20) // 4
@@ -311,11 +330,13 @@ def main():
     stats = bat.st.cpu().numpy()
     walk_steps = 0.0
     flops = 0.0
+    flops_full = 0.0
     for e, s in enumerate(envs):
         sl = slice(bat.off[e], bat.off[e + 1])
         ws = float((stats[sl, 9] * s["n_walks"]).sum())
         walk_steps += ws
-        flops += ws * distance_flops_per_step(s)
+        flops_full += ws * distance_flops_per_step(s)
+        flops += executed_distance_flops(s, stats[sl])
     value = walk_steps / (ms_step / 1e3)
     achieved = flops / (launch_ms / 1e3) / 1e12
     khash = kernel_hash()
@@ -340,13 +361,20 @@ def main():
                                   "512-env ragged batch (41660 q x 2048 walks, 16-2048 spheres)",
                       "envs": len(envs), "queries": int(bat.off[-1]),
                       "walks": int(sum(len(e["queries"]) * e["n_walks"] for e in envs)),
-                      "walk_steps_per_step": walk_steps, "eps": 1e-4, "seed": int(bat.seed)},
+                      "walk_steps_per_step": walk_steps, "eps": 1e-4, "seed": int(bat.seed),
+                      "obstacle_scan": "every obstacle" if args.full_scan else
+                                       "cluster-culled (exact: same walks as a full scan)"},
            "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
                         "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
                         "traffic": traffic,
                         "kernel": "persistent_kernel<fused fwd+bwd>",
                         "launch_ms": launch_ms,
                         "flops_per_launch": flops,
+                        "flops_basis": "distance operations executed (evaluated obstacles and cluster "
+                                       "bounds, counted by the kernel); a scan of every obstacle would "
+                                       "need full_scan_flops_per_launch",
+                        "full_scan_flops_per_launch": flops_full,
+                        "work_fraction": flops / flops_full,
                         "peak_basis": "MI355X FP32 vector peak, 157.3 TFLOP/s (datasheet); measured ceilings "
                                       "of this code's instruction types in 'measured'",
                         "measured": ceilings,
@@ -356,7 +384,7 @@ def main():
 
     if not args.no_plain:
         t = time.perf_counter()
-        pl = Plain(B, envs, bat.doms, torch, bat.seed)
+        pl = Plain(B, envs, bat.doms, torch, bat.seed, full_scan=args.full_scan)
         pl.run(only={len(envs) - 1})  # loads the plain kernels
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)

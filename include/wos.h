@@ -65,6 +65,8 @@ extern "C" {
 /* flags */
 #define WOS_FP32 0u
 #define WOS_FP64 1u
+#define WOS_FULL_SCAN 2u /* scan every obstacle each step (no cluster culling);
+                            same walks and results, more work: for testing */
 
 /* boundary-data modes */
 #define WOS_BDATA_CLASS 0  /* g_goal / g_obstacle / g_outer per component */
@@ -113,7 +115,7 @@ typedef struct {
 } wos_bdata;
 
 typedef struct {
-    uint32_t flags;     /* WOS_FP32 (default) or WOS_FP64 */
+    uint32_t flags;     /* WOS_FP32 (default) or WOS_FP64, optionally | WOS_FULL_SCAN */
     uint32_t env_id;    /* counter word 3 of the RNG (default 0) */
     uint32_t max_steps; /* distance evaluations per walk before truncation; 0 -> 65536 */
     uint32_t reserved;  /* must be 0 */
@@ -126,7 +128,10 @@ typedef struct {
  * components and their minimum).  goal may be NULL (no goal set); spheres
  * and boxes may be NULL (none).  The distance to the boundary is the minimum
  * of the components' signed distances; ties resolve to the goal, then spheres
- * by index, then boxes, then the outer boundary.
+ * by index, then boxes, then the outer boundary.  With 64 or more spheres
+ * (boxes) the domain also keeps them grouped in clusters of 8 with bounding
+ * spheres; the walk kernels skip a cluster that provably holds no nearer
+ * obstacle, which changes the work done, never a distance or a walk.
  * Errors: WOS_EDIM, WOS_EINVAL (NULL out/outer/bdata, non-finite values,
  * negative radii, empty box), WOS_ENOMEM, WOS_EHIP.
  */
@@ -196,8 +201,13 @@ int wos_backward(const wos_domain* dom, const void* queries, int64_t n_queries, 
  *   seed       Philox key; env e uses env_id = e
  *   out_u      device float, sum Q
  *   out_grad   device float, (sum Q) x 8, or NULL
- *   out_stats  device double, (sum Q) x 12, or NULL (layout of wos_estimate
- *              with d = 8 columns reserved for se_grad)
+ *   out_stats  device double, (sum Q) x 15, or NULL: columns 0..11 as
+ *              wos_estimate with d = 8 columns reserved for se_grad, then
+ *              [12] sphere distances evaluated per walk (mean),
+ *              [13] box distances evaluated per walk (mean),
+ *              [14] cluster bounds evaluated per walk (mean); these count
+ *              the work the obstacle scan did after culling (per walk they
+ *              wrap modulo 2^32)
  *   grad_u     device float, sum Q, or NULL for forward only
  *   out_dx     device float, (sum Q) x 8 (required with grad_u)
  *   out_dsigma device double, n_envs (required with grad_u)
@@ -276,6 +286,25 @@ int wos_set_autotune_cache(const char* cache_path);
 int wos_debug_walks(const wos_domain* dom, const double* query, uint32_t q_index, int64_t w0,
                     int64_t n, double sigma, double eps, uint64_t seed, const wos_options* opt,
                     double* out_records);
+
+/*
+ * wos_debug_clusters -- host only, no device: the obstacle clusters that
+ * wos_create_domain builds for this obstacle set (empty below 64 obstacles).
+ *   spheres, boxes   as wos_create_domain (either may be NULL)
+ *   fp64             0: the FP32 tables, 1: the FP64 tables
+ *   out_n_cl         host int64[2]: sphere clusters, box clusters
+ *   order_sph        host int64, capacity n_cl_sph * 8 (may be NULL): caller
+ *                    index of each clustered sphere row, -1 for padding
+ *   bnd_sph          host double, capacity n_cl_sph * (d + 1) (may be NULL):
+ *                    bounding sphere (centre, enlarged radius) per cluster,
+ *                    as stored in the device table
+ *   order_box, bnd_box  the same for boxes
+ * Capacities are taken from the counts this call computes: call once with
+ * NULL arrays to learn them.  Errors: WOS_EDIM, WOS_EINVAL.
+ */
+int wos_debug_clusters(int d, const wos_spheres* spheres, const wos_boxes* boxes, int fp64,
+                       int64_t* out_n_cl, int64_t* order_sph, double* bnd_sph, int64_t* order_box,
+                       double* bnd_box);
 
 /*
  * wos_microbench -- issue-rate microbenchmark on the current device, used as

@@ -18,7 +18,9 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libwos.so")
 
 WOS_OK, WOS_EINVAL, WOS_EDIM, WOS_ENOMEM, WOS_EHIP, WOS_ENOTSUP = 0, -1, -2, -3, -4, -5
-WOS_FP32, WOS_FP64 = 0, 1
+WOS_FP32, WOS_FP64, WOS_FULL_SCAN = 0, 1, 2
+CLUSTER = 8
+BATCH_STATS = 15
 WOS_OUTER_BOX, WOS_OUTER_BALL = 0, 1
 BATCH_STRIDE = 8
 MAX_DIM = 8
@@ -26,7 +28,7 @@ MAX_DIM = 8
 EXPORTED = ["wos_create_domain", "wos_destroy_domain", "wos_domain_dim", "wos_estimate",
             "wos_backward", "wos_estimate_batch", "wos_plan_create", "wos_plan_step",
             "wos_plan_buffers", "wos_plan_read", "wos_plan_destroy", "wos_autotune", "wos_set_autotune_cache",
-            "wos_debug_walks", "wos_microbench", "wos_last_error"]
+            "wos_debug_walks", "wos_debug_clusters", "wos_microbench", "wos_last_error"]
 
 
 class WosError(RuntimeError):
@@ -92,6 +94,8 @@ def _load():
     L.wos_set_autotune_cache.argtypes = [C.c_char_p]
     L.wos_debug_walks.argtypes = [vp, dp, u32, i64, i64, C.c_double, C.c_double, u64,
                                   C.POINTER(Options), dp]
+    L.wos_debug_clusters.argtypes = [C.c_int, C.POINTER(Spheres), C.POINTER(Boxes), C.c_int,
+                                     C.POINTER(i64), C.POINTER(i64), dp, C.POINTER(i64), dp]
     L.wos_microbench.argtypes = [C.c_int, dp, dp]
     L.wos_last_error.restype = C.c_char_p
     return L
@@ -132,8 +136,9 @@ def _stream(stream=None):
     return C.c_void_p(s.cuda_stream)
 
 
-def options(fp64=False, env_id=0, max_steps=0):
-    return Options(WOS_FP64 if fp64 else WOS_FP32, int(env_id), int(max_steps), 0)
+def options(fp64=False, env_id=0, max_steps=0, full_scan=False):
+    flags = (WOS_FP64 if fp64 else WOS_FP32) | (WOS_FULL_SCAN if full_scan else 0)
+    return Options(flags, int(env_id), int(max_steps), 0)
 
 
 # ---------------------------------------------------------------------------
@@ -230,6 +235,33 @@ def wos_debug_walks(dom, query, q_index, w0, n, sigma, eps, seed, opt=None):
                               float(eps), int(seed), C.byref(opt) if opt is not None else None,
                               _dp(out)))
     return out
+
+
+def wos_debug_clusters(d, sph_c=None, sph_r=None, box_c=None, box_h=None, fp64=False):
+    """Host-only cluster layout of an obstacle set: dict with, per kind
+    ('sph', 'box'), the caller index of each clustered row (-1: padding) and
+    the bounding spheres (n_cl x (d + 1): centre, enlarged radius)."""
+    keep = []
+    sp = bx = None
+    if sph_c is not None and len(sph_r):
+        c, r = _f64(sph_c), _f64(sph_r)
+        keep += [c, r]
+        sp = Spheres(len(r), _dp(c), _dp(r))
+    if box_c is not None and len(box_c):
+        c, h = _f64(box_c), _f64(box_h)
+        keep += [c, h]
+        bx = Boxes(len(c), _dp(c), _dp(h))
+    n_cl = (C.c_int64 * 2)()
+    args = (int(d), C.byref(sp) if sp else None, C.byref(bx) if bx else None, int(bool(fp64)))
+    check(lib.wos_debug_clusters(*args, n_cl, None, None, None, None))
+    ns, nb = n_cl[0], n_cl[1]
+    o_s = np.zeros(ns * CLUSTER, np.int64)
+    o_b = np.zeros(nb * CLUSTER, np.int64)
+    b_s = np.zeros((ns, d + 1))
+    b_b = np.zeros((nb, d + 1))
+    p64 = lambda a: a.ctypes.data_as(C.POINTER(C.c_int64))
+    check(lib.wos_debug_clusters(*args, n_cl, p64(o_s), _dp(b_s), p64(o_b), _dp(b_b)))
+    return {"sph": (o_s, b_s), "box": (o_b, b_b)}
 
 
 def wos_microbench(which):

@@ -15,6 +15,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <limits>
 #include <vector>
 
 #include "../../include/wos.h"
@@ -76,6 +77,12 @@ struct wos_domain {
     double g_goal = 1, g_obs = 0, g_outer = 0, b = 0;
     double ak[kMaxDim] = {0};
     double r_max = 0;  // largest possible empty-ball radius (bounds sigma R^2 / 4)
+    // clustered copies of the obstacle tables (see EnvP): one buffer per
+    // precision, [sphere rows | sphere bounds | box rows | box bounds]
+    int32_t n_cl_sph = 0, n_cl_box = 0;
+    float* cl_f = nullptr;
+    double* cl_d = nullptr;
+    size_t off_sph_bnd = 0, off_box_cl = 0, off_box_bnd = 0;
 };
 
 namespace {
@@ -99,7 +106,7 @@ int series_coeffs(double b, double y_max, double tol, double* c)
 
 template <typename T>
 int make_env(const wos_domain* D, double sigma, double eps, uint64_t seed, uint32_t env_id,
-             uint32_t max_steps, EnvP<T>& p)
+             const wos_options& o, EnvP<T>& p)
 {
     std::memset(&p, 0, sizeof(p));
     if (!(sigma >= 0.0) || !std::isfinite(sigma)) return fail(WOS_EINVAL, "sigma must be finite and >= 0 (got %g)", sigma);
@@ -130,6 +137,14 @@ int make_env(const wos_domain* D, double sigma, double eps, uint64_t seed, uint3
     }
     p.n_sph = (int32_t)D->n_sph;
     p.n_box = (int32_t)D->n_box;
+    const bool full = (o.flags & WOS_FULL_SCAN) != 0;
+    p.n_cl_sph = full ? 0 : D->n_cl_sph;
+    p.n_cl_box = full ? 0 : D->n_cl_box;
+    const T* cl = sizeof(T) == 4 ? (const T*)D->cl_f : (const T*)D->cl_d;
+    p.sph_cl = cl;
+    p.sph_bnd = cl ? cl + D->off_sph_bnd : nullptr;
+    p.box_cl = cl ? cl + D->off_box_cl : nullptr;
+    p.box_bnd = cl ? cl + D->off_box_bnd : nullptr;
     p.d = D->d;
     p.has_goal = D->has_goal ? 1 : 0;
     p.outer_kind = D->outer_kind;
@@ -139,7 +154,7 @@ int make_env(const wos_domain* D, double sigma, double eps, uint64_t seed, uint3
     p.key0 = (uint32_t)seed;
     p.key1 = (uint32_t)(seed >> 32);
     p.env_id = env_id;
-    p.max_steps = max_steps ? max_steps : kDefaultMaxSteps;
+    p.max_steps = o.max_steps ? o.max_steps : kDefaultMaxSteps;
     for (int i = 0; i < kMaxDim; ++i) {
         p.goal_c[i] = (T)D->goal_c[i];
         p.lo[i] = (T)D->lo[i];
@@ -163,6 +178,153 @@ int make_env(const wos_domain* D, double sigma, double eps, uint64_t seed, uint3
     return WOS_OK;
 }
 
+// Leaves of a k-d split of obstacle centres: the widest axis of the centres
+// in idx[lo, hi) is split at a multiple of kCluster near the median, so every
+// leaf but the last in order holds exactly kCluster obstacles.
+void kd_leaves(const double* c, int d, std::vector<int64_t>& idx, int64_t lo, int64_t hi)
+{
+    const int64_t n = hi - lo;
+    if (n <= kCluster) return;
+    double mn[kMaxDim], mx[kMaxDim];
+    for (int i = 0; i < d; ++i) {
+        mn[i] = INFINITY;
+        mx[i] = -INFINITY;
+    }
+    for (int64_t k = lo; k < hi; ++k)
+        for (int i = 0; i < d; ++i) {
+            mn[i] = std::min(mn[i], c[idx[k] * d + i]);
+            mx[i] = std::max(mx[i], c[idx[k] * d + i]);
+        }
+    int ax = 0;
+    for (int i = 1; i < d; ++i)
+        if (mx[i] - mn[i] > mx[ax] - mn[ax]) ax = i;
+    std::stable_sort(idx.begin() + lo, idx.begin() + hi,
+                     [&](int64_t a, int64_t b) { return c[a * d + ax] < c[b * d + ax]; });
+    int64_t half = (int64_t)std::llround((double)n / (2.0 * kCluster)) * kCluster;
+    half = std::min(std::max<int64_t>(half, kCluster), n - 1);
+    kd_leaves(c, d, idx, lo, lo + half);
+    kd_leaves(c, d, idx, lo + half, hi);
+}
+
+// Clustered rows and bounding spheres of one obstacle table in precision T.
+// rows: the caller-order table (stride S, values already rounded to T).  The
+// bounding radius is computed in FP64 from the rounded centres and radii
+// (spheres: r_j; boxes: |h_j|), enlarged by the relative margin 2 m of the
+// device bound (m = 2^-16 in FP32, 2^-45 in FP64) plus a tiny absolute term,
+// and rounded up to T.
+template <typename T>
+void build_clusters(int d, int64_t n, bool box, const std::vector<int64_t>& idx, const T* rows, int S,
+                    T* cl, T* bnd)
+{
+    const double m2 = sizeof(T) == 4 ? 0x1p-15 : 0x1p-44;
+    const double tiny = sizeof(T) == 4 ? 0x1p-100 : 0x1p-900;
+    const int SB = sph_stride(d);
+    const int64_t n_cl = (n + kCluster - 1) / kCluster;
+    for (int64_t g = 0; g < n_cl; ++g) {
+        const int64_t j0 = g * kCluster, j1 = std::min<int64_t>(n, j0 + kCluster);
+        double mn[kMaxDim], mx[kMaxDim];
+        for (int i = 0; i < d; ++i) {
+            mn[i] = INFINITY;
+            mx[i] = -INFINITY;
+        }
+        for (int64_t k = j0; k < j0 + kCluster; ++k) {
+            T* out = cl + k * S;
+            if (k < j1) {
+                const T* in = rows + idx[k] * S;
+                for (int i = 0; i < S; ++i) out[i] = in[i];
+                for (int i = 0; i < d; ++i) {
+                    mn[i] = std::min(mn[i], (double)in[i]);
+                    mx[i] = std::max(mx[i], (double)in[i]);
+                }
+            } else {
+                // padding: a point obstacle far outside any domain
+                for (int i = 0; i < S; ++i) out[i] = T(0);
+                for (int i = 0; i < d; ++i) out[i] = T(1e18);
+            }
+        }
+        T* b = bnd + g * SB;
+        for (int i = 0; i < SB; ++i) b[i] = T(0);
+        for (int i = 0; i < d; ++i) b[i] = (T)(0.5 * (mn[i] + mx[i]));
+        double rho = 0.0;
+        for (int64_t k = j0; k < j1; ++k) {
+            const T* in = rows + idx[k] * S;
+            double dc = 0.0, rad = 0.0;
+            for (int i = 0; i < d; ++i) {
+                const double t = (double)in[i] - (double)b[i];
+                dc += t * t;
+            }
+            if (box) {
+                for (int i = 0; i < d; ++i) rad += (double)in[d + i] * (double)in[d + i];
+                rad = std::sqrt(rad);
+            } else {
+                rad = (double)in[d];
+            }
+            rho = std::max(rho, std::sqrt(dc) + rad);
+        }
+        const double want = rho * (1.0 + m2) + tiny;
+        T r = (T)want;
+        if ((double)r < want) r = std::nextafter(r, std::numeric_limits<T>::infinity());
+        b[d] = r;
+    }
+}
+
+int check_obstacles(int d, const wos_spheres* spheres, const wos_boxes* boxes)
+{
+    const int64_t ns = spheres ? spheres->n : 0, nb = boxes ? boxes->n : 0;
+    if (ns < 0 || nb < 0 || ns > (1 << 24) || nb > (1 << 24)) return fail(WOS_EINVAL, "bad obstacle counts");
+    if (ns > 0 && (!spheres->centers || !spheres->radii)) return fail(WOS_EINVAL, "sphere arrays are NULL");
+    if (nb > 0 && (!boxes->centers || !boxes->half_widths)) return fail(WOS_EINVAL, "box arrays are NULL");
+    if (ns > 0 && (!finite_all(spheres->centers, ns * d) || !finite_all(spheres->radii, ns)))
+        return fail(WOS_EINVAL, "non-finite sphere data");
+    if (nb > 0 && (!finite_all(boxes->centers, nb * d) || !finite_all(boxes->half_widths, nb * d)))
+        return fail(WOS_EINVAL, "non-finite box data");
+    for (int64_t j = 0; j < ns; ++j)
+        if (spheres->radii[j] < 0) return fail(WOS_EINVAL, "negative sphere radius");
+    for (int64_t j = 0; j < nb * d; ++j)
+        if (boxes->half_widths[j] < 0) return fail(WOS_EINVAL, "negative box half-width");
+    return WOS_OK;
+}
+
+// Caller-order device rows of the obstacle tables in FP32 and FP64.
+void obstacle_rows(int d, const wos_spheres* spheres, const wos_boxes* boxes, std::vector<float>& sf,
+                   std::vector<double>& sd, std::vector<float>& bf, std::vector<double>& bd)
+{
+    const int64_t ns = spheres ? spheres->n : 0, nb = boxes ? boxes->n : 0;
+    const int ss = sph_stride(d), bs = box_stride(d);
+    sf.assign((size_t)std::max<int64_t>(ns, 1) * ss, 0.f);
+    sd.assign((size_t)std::max<int64_t>(ns, 1) * ss, 0.0);
+    for (int64_t j = 0; j < ns; ++j) {
+        for (int i = 0; i < d; ++i) {
+            sd[j * ss + i] = spheres->centers[j * d + i];
+            sf[j * ss + i] = (float)spheres->centers[j * d + i];
+        }
+        sd[j * ss + d] = spheres->radii[j];
+        sf[j * ss + d] = (float)spheres->radii[j];
+    }
+    bf.assign((size_t)std::max<int64_t>(nb, 1) * bs, 0.f);
+    bd.assign((size_t)std::max<int64_t>(nb, 1) * bs, 0.0);
+    for (int64_t j = 0; j < nb; ++j) {
+        for (int i = 0; i < d; ++i) {
+            bd[j * bs + i] = boxes->centers[j * d + i];
+            bf[j * bs + i] = (float)boxes->centers[j * d + i];
+            bd[j * bs + d + i] = boxes->half_widths[j * d + i];
+            bf[j * bs + d + i] = (float)boxes->half_widths[j * d + i];
+        }
+    }
+}
+
+// Cluster order of n obstacles (k-d leaves of kCluster), or none below
+// kClusterMin; returns the number of clusters.
+int64_t cluster_order(int d, int64_t n, const double* centers, std::vector<int64_t>& idx)
+{
+    idx.clear();
+    if (n < kClusterMin) return 0;
+    idx.resize(n);
+    for (int64_t j = 0; j < n; ++j) idx[j] = j;
+    kd_leaves(centers, d, idx, 0, n);
+    return (n + kCluster - 1) / kCluster;
+}
+
 int check_device(const wos_domain* D)
 {
     int dev = -1;
@@ -175,7 +337,7 @@ int read_opts(const wos_options* opt, wos_options& o)
 {
     o = wos_options{WOS_FP32, 0u, 0u, 0u};
     if (opt) o = *opt;
-    if (o.flags & ~1u) return fail(WOS_EINVAL, "unknown flags 0x%x", o.flags);
+    if (o.flags & ~(WOS_FP64 | WOS_FULL_SCAN)) return fail(WOS_EINVAL, "unknown flags 0x%x", o.flags);
     if (o.reserved != 0) return fail(WOS_EINVAL, "wos_options.reserved must be 0");
     return WOS_OK;
 }
@@ -342,7 +504,7 @@ struct BatchLayout {
 // launch has about units_per_wave units per resident wave; envs are ordered
 // by decreasing unit cost (longest-processing-time first).
 void plan_batch(const wos_domain* const* envs, const int64_t* q_off, int n_envs, const int64_t* n_walks,
-                int q_stride, int force_upw, int force_gm, BatchLayout& L)
+                int q_stride, int force_upw, int force_gm, bool full_scan, BatchLayout& L)
 {
     const int block = 256;
     int64_t sumQW = 0, maxM = 0, heavyQ = 0, maxW = 1;
@@ -396,6 +558,8 @@ void plan_batch(const wos_domain* const* envs, const int64_t* q_off, int n_envs,
         b.d = envs[e]->d;
         b.q_stride = q_stride;
         b.slot = e;
+        b.n_cl = full_scan ? 0 : envs[e]->n_cl_sph + envs[e]->n_cl_box;
+        b.pad = 0;
         b.unit_off = uoff;
         uoff += (int64_t)b.n_q * splits;
     }
@@ -429,10 +593,10 @@ int run_batch(const wos_domain* const* envs, int n_envs, const float* queries, c
         return fail(WOS_EINVAL, "out_dx, out_dsigma and out_dg are required with grad_u");
     std::vector<EnvP<float>> hp(n_envs);
     for (int e = 0; e < n_envs; ++e)
-        if ((rc = make_env<float>(envs[e], sigma[e], eps[e], seed, (uint32_t)e, o.max_steps, hp[e]))) return rc;
+        if ((rc = make_env<float>(envs[e], sigma[e], eps[e], seed, (uint32_t)e, o, hp[e]))) return rc;
 
     BatchLayout L;
-    plan_batch(envs, q_offsets, n_envs, n_walks, kBatchStride, force_upw, force_gm, L);
+    plan_batch(envs, q_offsets, n_envs, n_walks, kBatchStride, force_upw, force_gm, (o.flags & WOS_FULL_SCAN) != 0, L);
 
     Scratch S(st);
     // one upload: [EnvP x n_envs][BatchEnv x n_envs]
@@ -476,18 +640,9 @@ int wos_create_domain(int d, const wos_spheres* spheres, const wos_boxes* boxes,
     *out = nullptr;
     if (d < WOS_MIN_DIM || d > WOS_MAX_DIM) return fail(WOS_EDIM, "d = %d outside [%d, %d]", d, WOS_MIN_DIM, WOS_MAX_DIM);
     if (!outer || !bdata) return fail(WOS_EINVAL, "outer and bdata are required");
+    int rc = check_obstacles(d, spheres, boxes);
+    if (rc) return rc;
     const int64_t ns = spheres ? spheres->n : 0, nb = boxes ? boxes->n : 0;
-    if (ns < 0 || nb < 0 || ns > (1 << 24) || nb > (1 << 24)) return fail(WOS_EINVAL, "bad obstacle counts");
-    if (ns > 0 && (!spheres->centers || !spheres->radii)) return fail(WOS_EINVAL, "sphere arrays are NULL");
-    if (nb > 0 && (!boxes->centers || !boxes->half_widths)) return fail(WOS_EINVAL, "box arrays are NULL");
-    if (ns > 0 && (!finite_all(spheres->centers, ns * d) || !finite_all(spheres->radii, ns)))
-        return fail(WOS_EINVAL, "non-finite sphere data");
-    if (nb > 0 && (!finite_all(boxes->centers, nb * d) || !finite_all(boxes->half_widths, nb * d)))
-        return fail(WOS_EINVAL, "non-finite box data");
-    for (int64_t j = 0; j < ns; ++j)
-        if (spheres->radii[j] < 0) return fail(WOS_EINVAL, "negative sphere radius");
-    for (int64_t j = 0; j < nb * d; ++j)
-        if (boxes->half_widths[j] < 0) return fail(WOS_EINVAL, "negative box half-width");
     if (bdata->mode < 0 || bdata->mode > 2) return fail(WOS_EINVAL, "unknown boundary-data mode %d", bdata->mode);
     if (bdata->mode != 0 && !bdata->a_or_k) return fail(WOS_EINVAL, "a_or_k is required for mode %d", bdata->mode);
 
@@ -548,26 +703,9 @@ int wos_create_domain(int d, const wos_spheres* spheres, const wos_boxes* boxes,
 
     // device tables, FP32 and FP64, padded rows
     const int ss = sph_stride(d), bs = box_stride(d);
-    std::vector<float> sf((size_t)std::max<int64_t>(ns, 1) * ss, 0.f);
-    std::vector<double> sd((size_t)std::max<int64_t>(ns, 1) * ss, 0.0);
-    for (int64_t j = 0; j < ns; ++j) {
-        for (int i = 0; i < d; ++i) {
-            sd[j * ss + i] = spheres->centers[j * d + i];
-            sf[j * ss + i] = (float)spheres->centers[j * d + i];
-        }
-        sd[j * ss + d] = spheres->radii[j];
-        sf[j * ss + d] = (float)spheres->radii[j];
-    }
-    std::vector<float> bf((size_t)std::max<int64_t>(nb, 1) * bs, 0.f);
-    std::vector<double> bd((size_t)std::max<int64_t>(nb, 1) * bs, 0.0);
-    for (int64_t j = 0; j < nb; ++j) {
-        for (int i = 0; i < d; ++i) {
-            bd[j * bs + i] = boxes->centers[j * d + i];
-            bf[j * bs + i] = (float)boxes->centers[j * d + i];
-            bd[j * bs + d + i] = boxes->half_widths[j * d + i];
-            bf[j * bs + d + i] = (float)boxes->half_widths[j * d + i];
-        }
-    }
+    std::vector<float> sf, bf;
+    std::vector<double> sd, bd;
+    obstacle_rows(d, spheres, boxes, sf, sd, bf, bd);
     hipError_t e = hipGetDevice(&D->device);
     if (e == hipSuccess) e = hipMalloc(&D->sph_f, sf.size() * sizeof(float));
     if (e == hipSuccess) e = hipMalloc(&D->sph_d, sd.size() * sizeof(double));
@@ -577,6 +715,33 @@ int wos_create_domain(int d, const wos_spheres* spheres, const wos_boxes* boxes,
     if (e == hipSuccess) e = hipMemcpy(D->sph_d, sd.data(), sd.size() * sizeof(double), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(D->box_f, bf.data(), bf.size() * sizeof(float), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(D->box_d, bd.data(), bd.size() * sizeof(double), hipMemcpyHostToDevice);
+    // clustered tables for large obstacle sets
+    std::vector<int64_t> idx_s, idx_b;
+    D->n_cl_sph = (int32_t)cluster_order(d, ns, ns ? spheres->centers : nullptr, idx_s);
+    D->n_cl_box = (int32_t)cluster_order(d, nb, nb ? boxes->centers : nullptr, idx_b);
+    const int sb = sph_stride(d);
+    D->off_sph_bnd = (size_t)D->n_cl_sph * kCluster * ss;
+    D->off_box_cl = D->off_sph_bnd + (size_t)D->n_cl_sph * sb;
+    D->off_box_bnd = D->off_box_cl + (size_t)D->n_cl_box * kCluster * bs;
+    const size_t cl_elems = D->off_box_bnd + (size_t)D->n_cl_box * sb;
+    if (e == hipSuccess && cl_elems > 0) {
+        std::vector<float> cf(cl_elems);
+        std::vector<double> cd(cl_elems);
+        if (D->n_cl_sph) {
+            build_clusters<float>(d, ns, false, idx_s, sf.data(), ss, cf.data(), cf.data() + D->off_sph_bnd);
+            build_clusters<double>(d, ns, false, idx_s, sd.data(), ss, cd.data(), cd.data() + D->off_sph_bnd);
+        }
+        if (D->n_cl_box) {
+            build_clusters<float>(d, nb, true, idx_b, bf.data(), bs, cf.data() + D->off_box_cl,
+                                  cf.data() + D->off_box_bnd);
+            build_clusters<double>(d, nb, true, idx_b, bd.data(), bs, cd.data() + D->off_box_cl,
+                                   cd.data() + D->off_box_bnd);
+        }
+        e = hipMalloc(&D->cl_f, cl_elems * sizeof(float));
+        if (e == hipSuccess) e = hipMalloc(&D->cl_d, cl_elems * sizeof(double));
+        if (e == hipSuccess) e = hipMemcpy(D->cl_f, cf.data(), cl_elems * sizeof(float), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(D->cl_d, cd.data(), cl_elems * sizeof(double), hipMemcpyHostToDevice);
+    }
     if (e != hipSuccess) {
         wos_destroy_domain(D);
         return fail(e == hipErrorOutOfMemory ? WOS_ENOMEM : WOS_EHIP, "domain upload: %s", hipGetErrorString(e));
@@ -592,10 +757,53 @@ void wos_destroy_domain(wos_domain* D)
     (void)hipFree(D->sph_d);
     (void)hipFree(D->box_f);
     (void)hipFree(D->box_d);
+    (void)hipFree(D->cl_f);
+    (void)hipFree(D->cl_d);
     delete D;
 }
 
 int wos_domain_dim(const wos_domain* D) { return D ? D->d : fail(WOS_EINVAL, "domain is NULL"); }
+
+int wos_debug_clusters(int d, const wos_spheres* spheres, const wos_boxes* boxes, int fp64, int64_t* out_n_cl,
+                       int64_t* order_sph, double* bnd_sph, int64_t* order_box, double* bnd_box)
+{
+    if (d < WOS_MIN_DIM || d > WOS_MAX_DIM) return fail(WOS_EDIM, "d = %d outside [%d, %d]", d, WOS_MIN_DIM, WOS_MAX_DIM);
+    if (!out_n_cl) return fail(WOS_EINVAL, "out_n_cl is NULL");
+    int rc = check_obstacles(d, spheres, boxes);
+    if (rc) return rc;
+    const int64_t ns = spheres ? spheres->n : 0, nb = boxes ? boxes->n : 0;
+    std::vector<float> sf, bf;
+    std::vector<double> sd, bd;
+    obstacle_rows(d, spheres, boxes, sf, sd, bf, bd);
+    std::vector<int64_t> idx[2];
+    const int64_t n_cl[2] = {cluster_order(d, ns, ns ? spheres->centers : nullptr, idx[0]),
+                             cluster_order(d, nb, nb ? boxes->centers : nullptr, idx[1])};
+    out_n_cl[0] = n_cl[0];
+    out_n_cl[1] = n_cl[1];
+    const int64_t n[2] = {ns, nb};
+    const int S[2] = {sph_stride(d), box_stride(d)};
+    const int SB = sph_stride(d);
+    int64_t* order[2] = {order_sph, order_box};
+    double* bnd[2] = {bnd_sph, bnd_box};
+    for (int k = 0; k < 2; ++k) {
+        if (!n_cl[k]) continue;
+        if (order[k])
+            for (int64_t j = 0; j < n_cl[k] * kCluster; ++j) order[k][j] = j < n[k] ? idx[k][j] : -1;
+        if (!bnd[k]) continue;
+        std::vector<double> b((size_t)n_cl[k] * SB);
+        if (fp64) {
+            std::vector<double> cl((size_t)n_cl[k] * kCluster * S[k]);
+            build_clusters<double>(d, n[k], k == 1, idx[k], k ? bd.data() : sd.data(), S[k], cl.data(), b.data());
+        } else {
+            std::vector<float> cl((size_t)n_cl[k] * kCluster * S[k]), bf32((size_t)n_cl[k] * SB);
+            build_clusters<float>(d, n[k], k == 1, idx[k], k ? bf.data() : sf.data(), S[k], cl.data(), bf32.data());
+            for (size_t i = 0; i < b.size(); ++i) b[i] = bf32[i];
+        }
+        for (int64_t g = 0; g < n_cl[k]; ++g)
+            for (int i = 0; i <= d; ++i) bnd[k][g * (d + 1) + i] = b[g * SB + i];
+    }
+    return WOS_OK;
+}
 
 static int estimate_impl(const wos_domain* D, const void* queries, int64_t Q, int64_t n_walks, double sigma,
                          double eps, uint64_t seed, void* out_u, void* out_grad, double* out_stats,
@@ -625,7 +833,7 @@ static int estimate_impl(const wos_domain* D, const void* queries, int64_t Q, in
     if (bwd && (rc = S.get(&prod, (size_t)std::max<int64_t>(Q, 1) * 2))) return rc;
     if (o.flags & WOS_FP64) {
         EnvP<double> p;
-        if ((rc = make_env<double>(D, sigma, eps, seed, o.env_id, o.max_steps, p))) return rc;
+        if ((rc = make_env<double>(D, sigma, eps, seed, o.env_id, o, p))) return rc;
         if (Q == 0) {
             if (bwd) {
                 WOS_HIP(launch_fill_f64(out_dsigma, 1, 0.0, st), "fill");
@@ -648,7 +856,7 @@ static int estimate_impl(const wos_domain* D, const void* queries, int64_t Q, in
                 "finalize");
     } else {
         EnvP<float> p;
-        if ((rc = make_env<float>(D, sigma, eps, seed, o.env_id, o.max_steps, p))) return rc;
+        if ((rc = make_env<float>(D, sigma, eps, seed, o.env_id, o, p))) return rc;
         if (Q == 0) {
             if (bwd) {
                 WOS_HIP(launch_fill_f64(out_dsigma, 1, 0.0, st), "fill");
@@ -721,7 +929,7 @@ int wos_debug_walks(const wos_domain* D, const double* query, uint32_t q_index, 
         if (o.flags & WOS_FP64) {
             e = hipMemcpy(dq, query, d * sizeof(double), hipMemcpyHostToDevice);
             EnvP<double> p;
-            rc = make_env<double>(D, sigma, eps, seed, o.env_id, o.max_steps, p);
+            rc = make_env<double>(D, sigma, eps, seed, o.env_id, o, p);
             void* pd = nullptr;
             if (!rc && e == hipSuccess) e = hipMalloc(&pd, sizeof(p));
             if (!rc && e == hipSuccess) e = hipMemcpy(pd, &p, sizeof(p), hipMemcpyHostToDevice);
@@ -735,7 +943,7 @@ int wos_debug_walks(const wos_domain* D, const double* query, uint32_t q_index, 
             for (int i = 0; i < d; ++i) qf[i] = (float)query[i];
             e = hipMemcpy(dq, qf, d * sizeof(float), hipMemcpyHostToDevice);
             EnvP<float> p;
-            rc = make_env<float>(D, sigma, eps, seed, o.env_id, o.max_steps, p);
+            rc = make_env<float>(D, sigma, eps, seed, o.env_id, o, p);
             void* pd = nullptr;
             if (!rc && e == hipSuccess) e = hipMalloc(&pd, sizeof(p));
             if (!rc && e == hipSuccess) e = hipMemcpy(pd, &p, sizeof(p), hipMemcpyHostToDevice);
@@ -819,7 +1027,7 @@ int wos_plan_create(const wos_domain* D, float* x, int64_t n_starts, int64_t n_w
     P->d = D->d;
     P->S = n_starts;
     P->x = x;
-    if ((rc = make_env<float>(D, sigma, eps, seed, o.env_id, o.max_steps, P->henv))) {
+    if ((rc = make_env<float>(D, sigma, eps, seed, o.env_id, o, P->henv))) {
         delete P;
         return rc;
     }
@@ -834,7 +1042,7 @@ int wos_plan_create(const wos_domain* D, float* x, int64_t n_starts, int64_t n_w
     const int64_t qoff[2] = {0, n_starts};
     const int64_t nw[1] = {n_walks};
     BatchLayout L;
-    plan_batch(envs, qoff, 1, nw, D->d, 0, 0, L);
+    plan_batch(envs, qoff, 1, nw, D->d, 0, 0, (o.flags & WOS_FULL_SCAN) != 0, L);
     const int64_t S = n_starts;
     if (e == hipSuccess) e = hipMalloc(&P->u, S * sizeof(float));
     if (e == hipSuccess) e = hipMalloc(&P->grad, S * kBatchStride * sizeof(float));

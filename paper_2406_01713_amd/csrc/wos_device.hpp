@@ -246,14 +246,67 @@ __device__ __forceinline__ T outer_dist(cenv<T> p, const T (&x)[D])
     return p->orad - Math<T>::sqrt(acc);
 }
 
-// R = distance to the boundary; cls = first component attaining it in the
-// order goal, spheres, boxes, outer.
-template <typename T, int D>
-__device__ __forceinline__ T distance(cenv<T> p, const T (&x)[D], int& cls)
+// ------------------------------------------------------------------------
+// Cluster culling.  For a cluster with bounding sphere (C, rho), every member
+// distance (sphere: |x - c_j| - r_j; box SDF, which is at least
+// |x - c_j| - |h_j|) is, in exact arithmetic, at least |x - C| - rho when
+// rho >= |c_j - C| + r_j (or + |h_j|).  The computed bound
+//     lb = |x - C| (1 - m) - rho',   rho' = rho (1 + 2m) rounded up,
+// with m = 2^-16 (FP32) or 2^-45 (FP64), i.e. 256 units of rounding, is below
+// the computed member distance by more than every rounding error of either
+// value (each a few units relative to |x - C| + 2 rho).  So lb > t proves that
+// every member's computed distance exceeds t.
+// ------------------------------------------------------------------------
+template <typename T>
+struct Cull;
+template <>
+struct Cull<float> {
+    static constexpr float shrink = 1.0f - 0x1p-16f;
+};
+template <>
+struct Cull<double> {
+    static constexpr double shrink = 1.0 - 0x1p-45;
+};
+
+// Min over the members of the clusters that some active lane of the wave may
+// need: a cluster is evaluated (all kCluster rows, for every active lane) unless
+// its bound exceeds min(thr, running min) on every active lane.  thr is a
+// distance this lane's result cannot exceed (the goal, outer and box
+// distances already computed), so a skipped member is never the minimum and
+// never ties it.  ev counts the member distances evaluated.
+template <typename T, int D, bool BOX>
+__device__ __forceinline__ T cluster_min(cptr<T> rows, cptr<T> bnd, int n_cl, const T (&x)[D], T thr,
+                                         uint32_t& ev)
 {
-    const T ds = spheres_min<T, D>(to_const(p->sph), p->n_sph, x);
-    const T db = boxes_min<T, D>(to_const(fresh(p)->box), fresh(p)->n_box, x);
-    p = fresh(p);
+    constexpr int S = BOX ? box_stride(D) : sph_stride(D);
+    constexpr int SB = sph_stride(D);
+    T best = Math<T>::inf();
+    for (int g = 0; g < n_cl; ++g) {
+        cptr<T> b = bnd + g * SB;
+        const T lb = Math<T>::fma(Math<T>::sqrt(sq_dist<T, D>(x, b)), Cull<T>::shrink, -b[D]);
+        const bool need = !(lb > Math<T>::min(thr, best));
+        if (__ballot(need) == 0) continue;  // wave-uniform: no lane can improve
+        cptr<T> r = rows + g * (kCluster * S);
+#pragma unroll
+        for (int j = 0; j < kCluster; ++j)
+            best = Math<T>::min(best, BOX ? box_dist<T, D>(x, r + j * S) : sphere_dist<T, D>(x, r + j * S));
+        ev += kCluster;
+    }
+    return best;
+}
+
+// Distance evaluations of one call, for the work statistics.
+struct DistCount {
+    uint32_t sph, box;
+};
+
+// R = distance to the boundary; cls = first component attaining it in the
+// order goal, spheres, boxes, outer.  The goal and outer distances come first
+// and bound the box scan, whose result then bounds the sphere scan; culled
+// clusters leave R and cls as a scan of every obstacle gives them.
+template <typename T, int D>
+__device__ __forceinline__ T distance(cenv<T> p, const T (&x)[D], int& cls, DistCount& ev)
+{
     T dg = Math<T>::inf();
     if (p->has_goal) {
         T t = x[0] - p->goal_c[0];
@@ -265,7 +318,25 @@ __device__ __forceinline__ T distance(cenv<T> p, const T (&x)[D], int& cls)
         }
         dg = Math<T>::sqrt(acc) - p->goal_r;
     }
-    const T dout = outer_dist<T, D>(p, x);
+    const T dout = outer_dist<T, D>(fresh(p), x);
+    p = fresh(p);
+    T db;
+    if (p->n_cl_box) {
+        db = cluster_min<T, D, true>(to_const(p->box_cl), to_const(fresh(p)->box_bnd), fresh(p)->n_cl_box, x,
+                                     Math<T>::min(dg, dout), ev.box);
+    } else {
+        db = boxes_min<T, D>(to_const(p->box), fresh(p)->n_box, x);
+        ev.box += (uint32_t)fresh(p)->n_box;
+    }
+    p = fresh(p);
+    T ds;
+    if (p->n_cl_sph) {
+        ds = cluster_min<T, D, false>(to_const(p->sph_cl), to_const(fresh(p)->sph_bnd), fresh(p)->n_cl_sph, x,
+                                      Math<T>::min(Math<T>::min(dg, dout), db), ev.sph);
+    } else {
+        ds = spheres_min<T, D>(to_const(p->sph), fresh(p)->n_sph, x);
+        ev.sph += (uint32_t)fresh(p)->n_sph;
+    }
     const T bo = Math<T>::min(db, dout);
     const T rest = Math<T>::min(ds, bo);
     cls = (dg <= rest) ? kGoal : (ds <= bo) ? kSphere : (db <= dout) ? kBox : kOuter;
@@ -398,6 +469,7 @@ struct Walker {
     T S;       // sum_{i < k} d ln C(R_i) / d sigma
     uint32_t k;
     uint32_t w;
+    DistCount ev;  // obstacle distances evaluated by this walk (wrap at 2^32)
 };
 
 template <typename T>
@@ -408,6 +480,7 @@ struct WalkEnd {
     T goal_w;   // W 1{goal}
     uint32_t steps;
     int32_t status, cls;
+    DistCount ev;
 };
 
 template <typename T, int D, int DA>
@@ -423,6 +496,8 @@ __device__ __forceinline__ void walker_start(Walker<T, DA>& s, const T (&xq)[DA]
     s.S = T(0);
     s.k = 0;
     s.w = w;
+    s.ev.sph = 0;
+    s.ev.box = 0;
 }
 
 // Returns true when the walk ended (e is then filled in).  (key0, key1) is
@@ -435,7 +510,7 @@ __device__ __forceinline__ bool walker_step(cenv<T> p0, Walker<T, DA>& s, uint32
     static_assert(DA >= D, "walker storage narrower than the dimension");
     const T(&x)[D] = reinterpret_cast<const T(&)[D]>(s.x);
     int cls;
-    const T R = distance<T, D>(fresh(p0), x, cls);
+    const T R = distance<T, D>(fresh(p0), x, cls, s.ev);
     cenv<T> p = fresh(p0);
     const uint32_t k = s.k;
     if (R < p->eps) {
@@ -448,6 +523,7 @@ __device__ __forceinline__ bool walker_step(cenv<T> p0, Walker<T, DA>& s, uint32
         e.gs = first ? T(0) : s.gfac * s.W1 * g;
         e.S = s.S;
         e.goal_w = (cls == kGoal) ? s.W : T(0);
+        e.ev = s.ev;
         return true;
     }
     if (k + 1 >= p->max_steps) {
@@ -458,6 +534,7 @@ __device__ __forceinline__ bool walker_step(cenv<T> p0, Walker<T, DA>& s, uint32
         e.gs = T(0);
         e.S = T(0);
         e.goal_w = T(0);
+        e.ev = s.ev;
         return true;
     }
     const T R2 = R * R;

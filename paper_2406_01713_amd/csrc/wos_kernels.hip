@@ -66,6 +66,8 @@ __device__ __forceinline__ void accumulate(double (&a)[nacc(DA)], const WalkEnd<
     a[4 + 2 * DA] += (e.status == kDegenerate) ? 1.0 : 0.0;
     a[5 + 2 * DA] += u * (double)e.S;
     a[6 + 2 * DA] += (double)e.goal_w;
+    a[7 + 2 * DA] += (double)e.ev.sph;
+    a[8 + 2 * DA] += (double)e.ev.box;
 }
 
 // ------------------------------------------------------------------------
@@ -100,6 +102,7 @@ plain_kernel(const EnvP<T>* penv, const T* __restrict__ queries, int64_t n_units
     e.steps = 0;
     e.status = kTruncated;
     e.cls = kOuter;
+    e.ev.sph = e.ev.box = 0;
     if (active) {
         while (!walker_step<T, D, BWD>(p, s, q_base + (uint32_t)q, k0, k1, e)) {
         }
@@ -351,12 +354,15 @@ finalize_batch(const BatchEnv* __restrict__ benv, const double* __restrict__ par
         if (out_grad)
             for (int i = 0; i < M; ++i) out_grad[qg * grad_stride + i] = (i < d) ? (float)(a[2 + i] / n) : 0.0f;
         if (out_stats) {
-            double* st = out_stats + qg * (M + 4);
+            double* st = out_stats + qg * kBatchStats;
             st[0] = se_of(a[0], a[1], n);
             for (int i = 0; i < M; ++i) st[1 + i] = (i < d) ? se_of(a[2 + i], a[2 + M + i], n) : 0.0;
             st[M + 1] = a[2 + 2 * M] / n;
             st[M + 2] = a[3 + 2 * M];
             st[M + 3] = a[4 + 2 * M];
+            st[M + 4] = a[7 + 2 * M] / n;                    // sphere distances per walk
+            st[M + 5] = a[8 + 2 * M] / n;                    // box distances per walk
+            st[M + 6] = (a[2 + 2 * M] / n) * (double)be.n_cl;  // cluster bounds per walk
         }
         if (BWD) {
             const double ub = (double)ubar[qg];
@@ -401,7 +407,8 @@ plan_update(const EnvP<float>* penv, float* __restrict__ x, int64_t n, const flo
 #pragma unroll
         for (int i = 0; i < D; ++i) xs[i] = x[s * D + i];
         int cls;
-        const float R = distance<float, D>(p, xs, cls);
+        DistCount ev{0u, 0u};
+        const float R = distance<float, D>(p, xs, cls, ev);
         if (R < p->eps) {
             status[s] = (cls == kGoal) ? 1 : 2;
         } else {

@@ -10,6 +10,7 @@ constexpr int kMaxTerms = 96;      // Horner terms of the 0F1 weight series
 constexpr int kBatchStride = 8;    // row stride of batched query / gradient arrays
 constexpr int kWave = 64;          // CDNA wavefront width
 constexpr uint32_t kDefaultMaxSteps = 1u << 16;
+constexpr int kBatchStats = 15;    // columns of a batched stats row
 
 enum Class : int32_t { kGoal = 0, kSphere = 1, kBox = 2, kOuter = 3 };
 enum Status : int32_t { kAbsorbed = 0, kDegenerate = 1, kTruncated = 2 };
@@ -20,13 +21,28 @@ enum Status : int32_t { kAbsorbed = 0, kDegenerate = 1, kTruncated = 2 };
 __host__ __device__ constexpr int sph_stride(int d) { return ((d + 1 + 3) / 4) * 4; }
 __host__ __device__ constexpr int box_stride(int d) { return ((2 * d + 3) / 4) * 4; }
 
+// Obstacle clusters.  An environment with at least kClusterMin spheres (or
+// boxes) also holds them regrouped into clusters of kCluster rows (leaves of a
+// k-d split, the last one padded with rows far outside any domain), each with
+// a bounding sphere in sphere-row layout.  A wave skips a cluster when the
+// bound proves, for every active lane, that no member can be nearer than that
+// lane's current distance, so the distance (value and component) is the one
+// the full scan gives.
+constexpr int kCluster = 8;
+constexpr int kClusterMin = 64;
+
 // Per-environment parameters of one walk launch.  Read by every lane with
 // wave-uniform addresses, so the compiler keeps them in scalar registers.
 template <typename T>
 struct EnvP {
-    const T* sph;          // n_sph x sph_stride(d)
-    const T* box;          // n_box x box_stride(d)
+    const T* sph;          // n_sph x sph_stride(d), caller's order
+    const T* box;          // n_box x box_stride(d), caller's order
+    const T* sph_cl;       // n_cl_sph x kCluster sphere rows, cluster order
+    const T* box_cl;       // n_cl_box x kCluster box rows, cluster order
+    const T* sph_bnd;      // n_cl_sph bounding spheres, sph_stride(d) each
+    const T* box_bnd;      // n_cl_box bounding spheres, sph_stride(d) each
     int32_t n_sph, n_box;
+    int32_t n_cl_sph, n_cl_box;  // 0: scan the caller-order table instead
     int32_t d, has_goal;
     int32_t outer_kind, mode;  // outer: 0 box, 1 ball; mode: 0 class, 1 affine, 2 plane
     int32_t nt_C, nt_C1;       // Horner terms of 0F1(;d/2;y) and 0F1(;d/2+1;y)
@@ -55,12 +71,15 @@ struct BatchEnv {
     int32_t d;
     int32_t q_stride;   // row stride of the query array (elements)
     int32_t slot;       // position of the env in the caller's env array
+    int32_t n_cl;       // cluster bounds evaluated per walk-step (spheres + boxes)
+    int32_t pad;
 };
 
 // Accumulator layout of one work unit's partial sums (doubles):
 // [0] sum u, [1] sum u^2, [2, 2+d) sum grad, [2+d, 2+2d) sum grad^2,
 // [2+2d] sum steps, [3+2d] truncated, [4+2d] degenerate,
-// [5+2d] sum u*S (d u/d sigma), [6+2d] sum W 1{goal} (d u/d g_goal).
-__host__ __device__ constexpr int nacc(int d) { return 7 + 2 * d; }
+// [5+2d] sum u*S (d u/d sigma), [6+2d] sum W 1{goal} (d u/d g_goal),
+// [7+2d] sphere distances evaluated, [8+2d] box distances evaluated.
+__host__ __device__ constexpr int nacc(int d) { return 9 + 2 * d; }
 
 }  // namespace wos

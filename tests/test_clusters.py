@@ -1,0 +1,189 @@
+"""Host-side checks of the obstacle clusters the walk kernels cull with (no
+GPU): the cluster order is a permutation with padding only at the end, every
+member lies inside its cluster's bounding sphere, and the culling test
+|x - C| (1 - m) - rho' never exceeds a member's distance as the kernels
+compute it (emulated here operation by operation in the table's precision)."""
+import numpy as np
+import pytest
+
+from paper_2406_01713_amd import scenes as S
+
+CL = 8
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_2406_01713_amd import binding
+    return binding
+
+
+def _sets():
+    c3 = S.scene_c3(n_walks=16)
+    c5 = S.scene_c5(n_starts=4, n_walks=16)
+    big = S.scene_c4_env(5, n_walks=16, q_cap=4)
+    return [("c3", c3), ("c5", c5), (big["name"], big)]
+
+
+@pytest.mark.parametrize("fp64", [False, True])
+def test_cluster_order_is_a_padded_permutation(B, fp64):
+    for name, s in _sets():
+        out = B.wos_debug_clusters(s["d"], s["sph_c"], s["sph_r"], s["box_c"], s["box_h"], fp64=fp64)
+        for kind, n in (("sph", len(s["sph_r"])), ("box", len(s["box_c"]))):
+            order, bnd = out[kind]
+            if n < 64:
+                assert len(order) == 0 and len(bnd) == 0
+                continue
+            n_cl = -(-n // CL)
+            assert len(order) == n_cl * CL and bnd.shape == (n_cl, s["d"] + 1)
+            assert np.array_equal(np.sort(order[:n]), np.arange(n)), name
+            assert np.all(order[n:] == -1), name
+
+
+def test_small_sets_are_not_clustered(B):
+    rng = np.random.default_rng(0)
+    for n in (0, 1, 63):
+        out = B.wos_debug_clusters(3, rng.normal(size=(n, 3)), rng.uniform(0.1, 0.2, n))
+        assert len(out["sph"][0]) == 0
+    out = B.wos_debug_clusters(3, rng.normal(size=(64, 3)), rng.uniform(0.1, 0.2, 64))
+    assert len(out["sph"][0]) == 64
+
+
+def _rounded(a, fp64):
+    return np.asarray(a, np.float64) if fp64 else np.asarray(a, np.float32).astype(np.float64)
+
+
+@pytest.mark.parametrize("fp64", [False, True])
+def test_members_inside_bounds(B, fp64):
+    """rho' >= (|c_j - C| + r_j) (1 + 2^-15 in FP32) for every member, in FP64
+    on the values the device tables hold (boxes: r_j = |h_j|)."""
+    rel = 2.0 ** -44 if fp64 else 2.0 ** -15
+    for name, s in _sets():
+        out = B.wos_debug_clusters(s["d"], s["sph_c"], s["sph_r"], s["box_c"], s["box_h"], fp64=fp64)
+        for kind in ("sph", "box"):
+            order, bnd = out[kind]
+            if len(order) == 0:
+                continue
+            if kind == "sph":
+                c, rad = _rounded(s["sph_c"], fp64), _rounded(s["sph_r"], fp64)
+            else:
+                c = _rounded(s["box_c"], fp64)
+                rad = np.sqrt((_rounded(s["box_h"], fp64) ** 2).sum(1))
+            for g in range(len(bnd)):
+                m = order[g * CL:(g + 1) * CL]
+                m = m[m >= 0]
+                need = np.linalg.norm(c[m] - bnd[g, :-1], axis=1) + rad[m]
+                assert np.all(bnd[g, -1] >= need.max() * (1 + rel)), (name, kind, g)
+
+
+def _f32_sqdist(x, c):
+    """FP32 sum of squared differences as the kernels form it: first product,
+    then fused multiply-adds (each rounded once to FP32)."""
+    t = (x[:, None, 0] - c[None, :, 0]).astype(np.float32)
+    acc = (t * t).astype(np.float32)
+    for i in range(1, x.shape[1]):
+        t = (x[:, None, i] - c[None, :, i]).astype(np.float32)
+        acc = (t.astype(np.float64) * t + acc).astype(np.float32)   # fma, exact product
+    return acc
+
+
+def _sphere_d32(x, c, r):
+    return (np.sqrt(_f32_sqdist(x, c)).astype(np.float32) - r[None, :]).astype(np.float32)
+
+
+def _box_d32(x, c, h):
+    q = (np.abs((x[:, None, :] - c[None]).astype(np.float32)) - h[None]).astype(np.float32)
+    qp = np.maximum(q, np.float32(0))
+    out2 = np.zeros(q.shape[:2], np.float32)
+    for i in range(q.shape[2]):
+        out2 = (qp[..., i].astype(np.float64) * qp[..., i] + out2).astype(np.float32)
+    inside = q.max(2)
+    return (np.sqrt(out2).astype(np.float32) + np.minimum(inside, np.float32(0))).astype(np.float32)
+
+
+def _probe_points(rng, c, rad, d, n):
+    """Points on, just off, well off and inside member boundaries, plus
+    uniform points of the outer box."""
+    j = rng.integers(0, len(c), n)
+    v = rng.normal(size=(n, d))
+    v /= np.linalg.norm(v, axis=1, keepdims=True)
+    off = rng.choice([-0.5, -1e-4, 0.0, 1e-6, 1e-4, 1e-2, 0.3, 2.0], n)
+    pts = c[j] + v * (rad[j] * (1 + off) + off)[:, None]
+    uni = rng.uniform(-np.pi, np.pi, size=(n, d))
+    return np.concatenate([pts, uni])
+
+
+def test_cull_test_is_sound_in_fp32(B):
+    """Wherever the FP32 bound says "no member below t" (lb > t), every
+    member's FP32 distance exceeds lb, so it exceeds t."""
+    shrink = np.float32(1.0 - 2.0 ** -16)
+    rng = np.random.default_rng(3)
+    for name, s in _sets():
+        d = s["d"]
+        out = B.wos_debug_clusters(d, s["sph_c"], s["sph_r"], s["box_c"], s["box_h"])
+        for kind in ("sph", "box"):
+            order, bnd = out[kind]
+            if len(order) == 0:
+                continue
+            if kind == "sph":
+                c = np.asarray(s["sph_c"], np.float32)
+                r = np.asarray(s["sph_r"], np.float32)
+                rad = r.astype(np.float64)
+            else:
+                c = np.asarray(s["box_c"], np.float32)
+                h = np.asarray(s["box_h"], np.float32)
+                rad = np.sqrt((h.astype(np.float64) ** 2).sum(1))
+            x = _probe_points(rng, c.astype(np.float64), rad, d, 1500).astype(np.float32)
+            bc = bnd[:, :-1].astype(np.float32)
+            br = bnd[:, -1].astype(np.float32)
+            s_ = np.sqrt(_f32_sqdist(x, bc)).astype(np.float32)
+            lb = (s_.astype(np.float64) * shrink - br[None, :]).astype(np.float32)   # fma
+            dist = _sphere_d32(x, c, r) if kind == "sph" else _box_d32(x, c, h)
+            worst = np.inf
+            for g in range(len(bnd)):
+                m = order[g * CL:(g + 1) * CL]
+                m = m[m >= 0]
+                gap = dist[:, m].min(1).astype(np.float64) - lb[:, g]
+                worst = min(worst, gap.min())
+            assert worst > 0, (name, kind, worst)
+
+
+def test_cull_test_is_sound_in_fp64(B):
+    shrink = 1.0 - 2.0 ** -45
+    rng = np.random.default_rng(4)
+    for name, s in _sets():
+        d = s["d"]
+        out = B.wos_debug_clusters(d, s["sph_c"], s["sph_r"], s["box_c"], s["box_h"], fp64=True)
+        order, bnd = out["sph"]
+        if len(order) == 0:
+            continue
+        c, r = np.asarray(s["sph_c"]), np.asarray(s["sph_r"])
+        x = _probe_points(rng, c, r, d, 1000)
+        dist = np.sqrt(((x[:, None] - c[None]) ** 2).sum(2)) - r[None]
+        lb = np.sqrt(((x[:, None] - bnd[None, :, :-1]) ** 2).sum(2)) * shrink - bnd[None, :, -1]
+        for g in range(len(bnd)):
+            m = order[g * CL:(g + 1) * CL]
+            m = m[m >= 0]
+            assert np.all(dist[:, m].min(1) > lb[:, g]), (name, g)
+
+
+def test_bounds_cull_far_points(B):
+    """The bounds are not vacuous: from a point far outside an obstacle set
+    most clusters are provably farther than the nearest obstacle."""
+    s = S.scene_c4_env(5, n_walks=16, q_cap=4)
+    d = s["d"]
+    out = B.wos_debug_clusters(d, s["sph_c"], s["sph_r"])
+    order, bnd = out["sph"]
+    c, r = np.asarray(s["sph_c"]), np.asarray(s["sph_r"])
+    x = np.asarray(s["queries"][:4])
+    R = (np.sqrt(((x[:, None] - c[None]) ** 2).sum(2)) - r[None]).min(1)
+    lb = np.sqrt(((x[:, None] - bnd[None, :, :-1]) ** 2).sum(2)) - bnd[None, :, -1]
+    assert (lb > R[:, None]).mean() > 0.3
+
+
+def test_debug_clusters_rejects_bad_input(B):
+    import ctypes as C
+    n = (C.c_int64 * 2)()
+    assert B.lib.wos_debug_clusters(9, None, None, 0, n, None, None, None, None) == B.WOS_EDIM
+    assert B.lib.wos_debug_clusters(3, None, None, 0, None, None, None, None, None) == B.WOS_EINVAL
+    with pytest.raises(B.WosError):
+        B.wos_debug_clusters(3, np.zeros((70, 3)), -np.ones(70))

@@ -30,7 +30,7 @@ def dev(a, dtype):
 
 
 def gpu_estimate(B, scene, fp64=False, queries=None, n_walks=None, seed=None, env_id=0,
-                 max_steps=0, sigma=None, eps=None):
+                 max_steps=0, sigma=None, eps=None, full_scan=False):
     import torch
     dt = torch.float64 if fp64 else torch.float32
     dom = B.Domain(scene)
@@ -42,7 +42,7 @@ def gpu_estimate(B, scene, fp64=False, queries=None, n_walks=None, seed=None, en
     B.wos_estimate(dom, q, scene["n_walks"] if n_walks is None else n_walks,
                    scene["sigma"] if sigma is None else sigma, scene["eps"] if eps is None else eps,
                    scene["seed"] if seed is None else seed, u, g, st,
-                   opt=B.options(fp64, env_id, max_steps))
+                   opt=B.options(fp64, env_id, max_steps, full_scan=full_scan))
     torch.cuda.synchronize()
     return u.cpu().numpy().astype(np.float64), g.cpu().numpy().astype(np.float64), st.cpu().numpy()
 
@@ -254,7 +254,7 @@ def _ragged(n_envs=10, q_cap=24, n_walks=512):
     return envs
 
 
-def gpu_batch(B, envs, n_walks, seed, ubar=None, torch_dtype=None):
+def gpu_batch(B, envs, n_walks, seed, ubar=None, torch_dtype=None, full_scan=False):
     import torch
     doms = [B.Domain(e) for e in envs]
     Qs = [len(e["queries"]) for e in envs]
@@ -266,14 +266,14 @@ def gpu_batch(B, envs, n_walks, seed, ubar=None, torch_dtype=None):
     n = int(off[-1])
     u = torch.empty(n, device="cuda")
     g = torch.empty(n, 8, device="cuda")
-    st = torch.empty(n, 12, dtype=torch.float64, device="cuda")
+    st = torch.empty(n, 15, dtype=torch.float64, device="cuda")
     kw = {}
     if ubar is not None:
         kw = dict(grad_u=dev(ubar, torch.float32), out_dx=torch.empty(n, 8, device="cuda"),
                   out_dsigma=torch.empty(len(envs), dtype=torch.float64, device="cuda"),
                   out_dg=torch.empty(len(envs), dtype=torch.float64, device="cuda"))
     B.wos_estimate_batch(doms, q, off, [e["sigma"] for e in envs], [e["eps"] for e in envs], n_walks,
-                         seed, u, g, st, **kw)
+                         seed, u, g, st, opt=B.options(full_scan=full_scan), **kw)
     torch.cuda.synchronize()
     out = {"u": u.cpu().numpy(), "g": g.cpu().numpy(), "st": st.cpu().numpy(), "off": off}
     if ubar is not None:
@@ -305,6 +305,59 @@ def test_batch_matches_plain_per_env(B):
         assert np.allclose(out["dx"][sl, :d], dx, rtol=2e-5, atol=1e-6), e
         assert out["ds"][e] == pytest.approx(ds, rel=1e-4, abs=1e-8)
         assert out["dg"][e] == pytest.approx(dg, rel=1e-4, abs=1e-8)
+
+
+def _cull_scenes():
+    big = S.scene_c4_env(5, n_walks=256, seed=2, q_cap=6)
+    return [subset("c3", 8, 256, seed=2), subset("c5", 6, 256, seed=2), big]
+
+
+@pytest.mark.parametrize("fp64", [False, True])
+def test_culling_changes_no_result_plain(B, fp64):
+    """Cluster culling skips only obstacles that cannot be nearest: every
+    walk, hence every output, is bitwise the one a scan of every obstacle
+    gives (spheres and boxes, FP32 and FP64)."""
+    for s in _cull_scenes():
+        assert len(s["sph_r"]) >= 64
+        a = gpu_estimate(B, s, fp64=fp64)
+        b = gpu_estimate(B, s, fp64=fp64, full_scan=True)
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y), s["name"]
+        dom = B.Domain(s)
+        for q in range(2):
+            ra = B.wos_debug_walks(dom, s["queries"][q], q, 0, 256, s["sigma"], s["eps"], s["seed"],
+                                   opt=B.options(fp64))
+            rb = B.wos_debug_walks(dom, s["queries"][q], q, 0, 256, s["sigma"], s["eps"], s["seed"],
+                                   opt=B.options(fp64, full_scan=True))
+            assert np.array_equal(ra, rb), (s["name"], q)
+
+
+def test_culling_changes_no_result_batch(B):
+    """Same in the persistent kernel, and the work columns of the stats
+    count what the scans did: a full scan evaluates M obstacles per step, a
+    culled one at most that plus one bound per cluster."""
+    envs = _ragged(n_envs=12, q_cap=16, n_walks=256)
+    rng = np.random.default_rng(9)
+    ubar = rng.normal(size=sum(len(e["queries"]) for e in envs)).astype(np.float32)
+    a = gpu_batch(B, envs, 256, 5, ubar=ubar)
+    b = gpu_batch(B, envs, 256, 5, ubar=ubar, full_scan=True)
+    for k in ("u", "g", "dx", "ds", "dg"):
+        assert np.array_equal(a[k], b[k]), k
+    assert np.array_equal(a["st"][:, :12], b["st"][:, :12])
+    saved = 0
+    for e, s in enumerate(envs):
+        sl = slice(a["off"][e], a["off"][e + 1])
+        M = len(s["sph_r"])
+        steps = b["st"][sl, 9]
+        assert np.allclose(b["st"][sl, 12], steps * M, rtol=1e-12)
+        assert np.all(b["st"][sl, 13] == 0) and np.all(b["st"][sl, 14] == 0)
+        if M < 64:
+            assert np.array_equal(a["st"][sl, 12:], b["st"][sl, 12:]), e
+        else:
+            assert np.allclose(a["st"][sl, 14], steps * -(-M // 8), rtol=1e-12)
+            assert np.all(a["st"][sl, 12] <= (-(-M // 8) * 8) * steps * (1 + 1e-12))
+            saved += (b["st"][sl, 12] - a["st"][sl, 12]).sum()
+    assert saved > 0
 
 
 def test_batch_vs_oracle(B, oracle):
