@@ -206,6 +206,70 @@ void kd_leaves(const double* c, int d, std::vector<int64_t>& idx, int64_t lo, in
     kd_leaves(c, d, idx, lo + half, hi);
 }
 
+// Reach of member k of a cluster from centre C: |c_k - C| + r_k (spheres)
+// or + |h_k| (boxes).
+template <typename T>
+double reach(int d, const T* row, bool box, const double* C)
+{
+    double dc = 0.0, rad = 0.0;
+    for (int i = 0; i < d; ++i) {
+        const double t = (double)row[i] - C[i];
+        dc += t * t;
+    }
+    if (box) {
+        for (int i = 0; i < d; ++i) rad += (double)row[d + i] * (double)row[d + i];
+        rad = std::sqrt(rad);
+    } else {
+        rad = (double)row[d];
+    }
+    return std::sqrt(dc) + rad;
+}
+
+// Centre that (nearly) minimises the bounding radius max_k reach_k(C), a
+// convex function of C: from the start point, step towards the member of
+// largest reach, keeping a step only when it lowers the maximum and
+// shrinking the step otherwise.  Any centre is valid; a smaller radius only
+// makes the bound tighter.
+template <typename T>
+void minimax_centre(int d, const T* rows, int S, bool box, const int64_t* members, int n, double* C)
+{
+    auto fmax = [&](const double* P, int* arg) {
+        double f = -1.0;
+        for (int k = 0; k < n; ++k) {
+            const double r = reach(d, rows + members[k] * S, box, P);
+            if (r > f) {
+                f = r;
+                *arg = k;
+            }
+        }
+        return f;
+    };
+    int far = 0;
+    double f = fmax(C, &far);
+    double step = 0.5 * f;
+    for (int it = 0; it < 64 && step > 0.0; ++it) {
+        const T* row = rows + members[far] * S;
+        double dir[kMaxDim], nrm = 0.0;
+        for (int i = 0; i < d; ++i) {
+            dir[i] = (double)row[i] - C[i];
+            nrm += dir[i] * dir[i];
+        }
+        nrm = std::sqrt(nrm);
+        if (nrm == 0.0) break;
+        double P[kMaxDim];
+        for (int i = 0; i < d; ++i) P[i] = C[i] + step * dir[i] / nrm;
+        int farP = 0;
+        const double fP = fmax(P, &farP);
+        if (fP < f) {
+            for (int i = 0; i < d; ++i) C[i] = P[i];
+            f = fP;
+            far = farP;
+        } else {
+            step *= 0.7;
+        }
+    }
+}
+
 // Clustered rows and bounding spheres of one obstacle table in precision T.
 // rows: the caller-order table (stride S, values already rounded to T).  The
 // bounding radius is computed in FP64 from the rounded centres and radii
@@ -244,23 +308,14 @@ void build_clusters(int d, int64_t n, bool box, const std::vector<int64_t>& idx,
         }
         T* b = bnd + g * SB;
         for (int i = 0; i < SB; ++i) b[i] = T(0);
-        for (int i = 0; i < d; ++i) b[i] = (T)(0.5 * (mn[i] + mx[i]));
+        double C[kMaxDim];
+        for (int i = 0; i < d; ++i) C[i] = 0.5 * (mn[i] + mx[i]);
+        minimax_centre(d, rows, S, box, idx.data() + j0, (int)(j1 - j0), C);
+        for (int i = 0; i < d; ++i) b[i] = (T)C[i];
         double rho = 0.0;
-        for (int64_t k = j0; k < j1; ++k) {
-            const T* in = rows + idx[k] * S;
-            double dc = 0.0, rad = 0.0;
-            for (int i = 0; i < d; ++i) {
-                const double t = (double)in[i] - (double)b[i];
-                dc += t * t;
-            }
-            if (box) {
-                for (int i = 0; i < d; ++i) rad += (double)in[d + i] * (double)in[d + i];
-                rad = std::sqrt(rad);
-            } else {
-                rad = (double)in[d];
-            }
-            rho = std::max(rho, std::sqrt(dc) + rad);
-        }
+        double Cr[kMaxDim];
+        for (int i = 0; i < d; ++i) Cr[i] = (double)b[i];  // the centre as stored
+        for (int64_t k = j0; k < j1; ++k) rho = std::max(rho, reach(d, rows + idx[k] * S, box, Cr));
         const double want = rho * (1.0 + m2) + tiny;
         T r = (T)want;
         if ((double)r < want) r = std::nextafter(r, std::numeric_limits<T>::infinity());
@@ -719,14 +774,17 @@ int wos_create_domain(int d, const wos_spheres* spheres, const wos_boxes* boxes,
     std::vector<int64_t> idx_s, idx_b;
     D->n_cl_sph = (int32_t)cluster_order(d, ns, ns ? spheres->centers : nullptr, idx_s);
     D->n_cl_box = (int32_t)cluster_order(d, nb, nb ? boxes->centers : nullptr, idx_b);
+    // bound tables hold one zero row past the last cluster, which the scan
+    // prefetches and never uses
     const int sb = sph_stride(d);
+    const size_t nbs = D->n_cl_sph ? (size_t)D->n_cl_sph + 1 : 0, nbb = D->n_cl_box ? (size_t)D->n_cl_box + 1 : 0;
     D->off_sph_bnd = (size_t)D->n_cl_sph * kCluster * ss;
-    D->off_box_cl = D->off_sph_bnd + (size_t)D->n_cl_sph * sb;
+    D->off_box_cl = D->off_sph_bnd + nbs * sb;
     D->off_box_bnd = D->off_box_cl + (size_t)D->n_cl_box * kCluster * bs;
-    const size_t cl_elems = D->off_box_bnd + (size_t)D->n_cl_box * sb;
+    const size_t cl_elems = D->off_box_bnd + nbb * sb;
     if (e == hipSuccess && cl_elems > 0) {
-        std::vector<float> cf(cl_elems);
-        std::vector<double> cd(cl_elems);
+        std::vector<float> cf(cl_elems, 0.f);
+        std::vector<double> cd(cl_elems, 0.0);
         if (D->n_cl_sph) {
             build_clusters<float>(d, ns, false, idx_s, sf.data(), ss, cf.data(), cf.data() + D->off_sph_bnd);
             build_clusters<double>(d, ns, false, idx_s, sd.data(), ss, cd.data(), cd.data() + D->off_sph_bnd);

@@ -268,12 +268,31 @@ struct Cull<double> {
     static constexpr double shrink = 1.0 - 0x1p-45;
 };
 
+template <typename T, int D>
+__device__ __forceinline__ T cluster_bound(const T (&x)[D], cptr<T> b)
+{
+    return Math<T>::fma(Math<T>::sqrt(sq_dist<T, D>(x, b)), Cull<T>::shrink, -b[D]);
+}
+
+template <typename T, int D, bool BOX>
+__device__ __forceinline__ T cluster_members_min(const T (&x)[D], cptr<T> r, T best)
+{
+    constexpr int S = BOX ? box_stride(D) : sph_stride(D);
+#pragma unroll
+    for (int j = 0; j < kCluster; ++j)
+        best = Math<T>::min(best, BOX ? box_dist<T, D>(x, r + j * S) : sphere_dist<T, D>(x, r + j * S));
+    return best;
+}
+
 // Min over the members of the clusters that some active lane of the wave may
 // need: a cluster is evaluated (all kCluster rows, for every active lane) unless
-// its bound exceeds min(thr, running min) on every active lane.  thr is a
-// distance this lane's result cannot exceed (the goal, outer and box
+// its bound exceeds thr or the running min on every active lane.  thr
+// is a distance this lane's result cannot exceed (the goal, outer and box
 // distances already computed), so a skipped member is never the minimum and
-// never ties it.  ev counts the member distances evaluated.
+// never ties it.  Bounds are taken two clusters at a time (the second against
+// the running min before the first cluster's members, which only culls
+// less); the bound table's spare row stands in for a missing second cluster.
+// NaN bounds never cull.  ev counts the member distances evaluated.
 template <typename T, int D, bool BOX>
 __device__ __forceinline__ T cluster_min(cptr<T> rows, cptr<T> bnd, int n_cl, const T (&x)[D], T thr,
                                          uint32_t& ev)
@@ -281,16 +300,18 @@ __device__ __forceinline__ T cluster_min(cptr<T> rows, cptr<T> bnd, int n_cl, co
     constexpr int S = BOX ? box_stride(D) : sph_stride(D);
     constexpr int SB = sph_stride(D);
     T best = Math<T>::inf();
-    for (int g = 0; g < n_cl; ++g) {
-        cptr<T> b = bnd + g * SB;
-        const T lb = Math<T>::fma(Math<T>::sqrt(sq_dist<T, D>(x, b)), Cull<T>::shrink, -b[D]);
-        const bool need = !(lb > Math<T>::min(thr, best));
-        if (__ballot(need) == 0) continue;  // wave-uniform: no lane can improve
-        cptr<T> r = rows + g * (kCluster * S);
-#pragma unroll
-        for (int j = 0; j < kCluster; ++j)
-            best = Math<T>::min(best, BOX ? box_dist<T, D>(x, r + j * S) : sphere_dist<T, D>(x, r + j * S));
-        ev += kCluster;
+    for (int g = 0; g < n_cl; g += 2) {
+        const T lb0 = cluster_bound<T, D>(x, bnd + g * SB);
+        const T lb1 = cluster_bound<T, D>(x, bnd + (g + 1) * SB);
+        const bool need1 = !(lb1 > thr || lb1 > best);
+        if (__ballot(!(lb0 > thr || lb0 > best)) != 0) {  // wave-uniform
+            best = cluster_members_min<T, D, BOX>(x, rows + g * (kCluster * S), best);
+            ev += kCluster;
+        }
+        if (g + 1 < n_cl && __ballot(need1) != 0) {
+            best = cluster_members_min<T, D, BOX>(x, rows + (g + 1) * (kCluster * S), best);
+            ev += kCluster;
+        }
     }
     return best;
 }

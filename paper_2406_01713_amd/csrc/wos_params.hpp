@@ -39,8 +39,8 @@ struct EnvP {
     const T* box;          // n_box x box_stride(d), caller's order
     const T* sph_cl;       // n_cl_sph x kCluster sphere rows, cluster order
     const T* box_cl;       // n_cl_box x kCluster box rows, cluster order
-    const T* sph_bnd;      // n_cl_sph bounding spheres, sph_stride(d) each
-    const T* box_bnd;      // n_cl_box bounding spheres, sph_stride(d) each
+    const T* sph_bnd;      // n_cl_sph + 1 bounding spheres, sph_stride(d) each (last: unused)
+    const T* box_bnd;      // n_cl_box + 1 bounding spheres, sph_stride(d) each (last: unused)
     int32_t n_sph, n_box;
     int32_t n_cl_sph, n_cl_box;  // 0: scan the caller-order table instead
     int32_t d, has_goal;
