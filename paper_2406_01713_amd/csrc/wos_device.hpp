@@ -292,10 +292,12 @@ __device__ __forceinline__ T cluster_members_min(const T (&x)[D], cptr<T> r, T b
 // never ties it.  Bounds are taken two clusters at a time (the second against
 // the running min before the first cluster's members, which only culls
 // less); the bound table's spare row stands in for a missing second cluster.
-// NaN bounds never cull.  ev counts the member distances evaluated.
+// NaN bounds never cull.  Lanes with live false (idle lanes that run along)
+// never demand a cluster.  n_eval (wave-uniform) counts the member distances
+// each lane evaluated.
 template <typename T, int D, bool BOX>
 __device__ __forceinline__ T cluster_min(cptr<T> rows, cptr<T> bnd, int n_cl, const T (&x)[D], T thr,
-                                         uint32_t& ev)
+                                         bool live, uint32_t& n_eval)
 {
     constexpr int S = BOX ? box_stride(D) : sph_stride(D);
     constexpr int SB = sph_stride(D);
@@ -303,22 +305,26 @@ __device__ __forceinline__ T cluster_min(cptr<T> rows, cptr<T> bnd, int n_cl, co
     for (int g = 0; g < n_cl; g += 2) {
         const T lb0 = cluster_bound<T, D>(x, bnd + g * SB);
         const T lb1 = cluster_bound<T, D>(x, bnd + (g + 1) * SB);
-        const bool need1 = !(lb1 > thr || lb1 > best);
-        if (__ballot(!(lb0 > thr || lb0 > best)) != 0) {  // wave-uniform
+        const bool need1 = live && !(lb1 > thr || lb1 > best);
+        if (__ballot(live && !(lb0 > thr || lb0 > best)) != 0) {  // wave-uniform
             best = cluster_members_min<T, D, BOX>(x, rows + g * (kCluster * S), best);
-            ev += kCluster;
+            n_eval += kCluster;
         }
         if (g + 1 < n_cl && __ballot(need1) != 0) {
             best = cluster_members_min<T, D, BOX>(x, rows + (g + 1) * (kCluster * S), best);
-            ev += kCluster;
+            n_eval += kCluster;
         }
     }
     return best;
 }
 
-// Distance evaluations of one call, for the work statistics.
-struct DistCount {
-    uint32_t sph, box;
+// Obstacle distances evaluated, summed over the live lanes of a wave: the
+// scans are wave-uniform, so every lane evaluates the same rows, and the
+// tally is one wave-level count for the work statistics.  Callers run the
+// step on every lane of the wave (idle lanes with live false), so the tally
+// is updated in wave-uniform control flow.
+struct WorkCount {
+    uint64_t sph, box;
 };
 
 // R = distance to the boundary; cls = first component attaining it in the
@@ -326,7 +332,7 @@ struct DistCount {
 // and bound the box scan, whose result then bounds the sphere scan; culled
 // clusters leave R and cls as a scan of every obstacle gives them.
 template <typename T, int D>
-__device__ __forceinline__ T distance(cenv<T> p, const T (&x)[D], int& cls, DistCount& ev)
+__device__ __forceinline__ T distance(cenv<T> p, const T (&x)[D], int& cls, WorkCount& wc, bool live)
 {
     T dg = Math<T>::inf();
     if (p->has_goal) {
@@ -342,22 +348,28 @@ __device__ __forceinline__ T distance(cenv<T> p, const T (&x)[D], int& cls, Dist
     const T dout = outer_dist<T, D>(fresh(p), x);
     p = fresh(p);
     T db;
+    uint32_t nb, ns;
     if (p->n_cl_box) {
+        nb = 0;
         db = cluster_min<T, D, true>(to_const(p->box_cl), to_const(fresh(p)->box_bnd), fresh(p)->n_cl_box, x,
-                                     Math<T>::min(dg, dout), ev.box);
+                                     Math<T>::min(dg, dout), live, nb);
     } else {
         db = boxes_min<T, D>(to_const(p->box), fresh(p)->n_box, x);
-        ev.box += (uint32_t)fresh(p)->n_box;
+        nb = (uint32_t)fresh(p)->n_box;
     }
     p = fresh(p);
     T ds;
     if (p->n_cl_sph) {
+        ns = 0;
         ds = cluster_min<T, D, false>(to_const(p->sph_cl), to_const(fresh(p)->sph_bnd), fresh(p)->n_cl_sph, x,
-                                      Math<T>::min(Math<T>::min(dg, dout), db), ev.sph);
+                                      Math<T>::min(Math<T>::min(dg, dout), db), live, ns);
     } else {
         ds = spheres_min<T, D>(to_const(p->sph), fresh(p)->n_sph, x);
-        ev.sph += (uint32_t)fresh(p)->n_sph;
+        ns = (uint32_t)fresh(p)->n_sph;
     }
+    const uint64_t lanes = (uint64_t)__popcll(__ballot(live));
+    wc.sph += lanes * ns;
+    wc.box += lanes * nb;
     const T bo = Math<T>::min(db, dout);
     const T rest = Math<T>::min(ds, bo);
     cls = (dg <= rest) ? kGoal : (ds <= bo) ? kSphere : (db <= dout) ? kBox : kOuter;
@@ -490,7 +502,6 @@ struct Walker {
     T S;       // sum_{i < k} d ln C(R_i) / d sigma
     uint32_t k;
     uint32_t w;
-    DistCount ev;  // obstacle distances evaluated by this walk (wrap at 2^32)
 };
 
 template <typename T>
@@ -501,7 +512,6 @@ struct WalkEnd {
     T goal_w;   // W 1{goal}
     uint32_t steps;
     int32_t status, cls;
-    DistCount ev;
 };
 
 template <typename T, int D, int DA>
@@ -517,8 +527,6 @@ __device__ __forceinline__ void walker_start(Walker<T, DA>& s, const T (&xq)[DA]
     s.S = T(0);
     s.k = 0;
     s.w = w;
-    s.ev.sph = 0;
-    s.ev.box = 0;
 }
 
 // Returns true when the walk ended (e is then filled in).  (key0, key1) is
@@ -526,12 +534,12 @@ __device__ __forceinline__ void walker_start(Walker<T, DA>& s, const T (&xq)[DA]
 // walker may store DA >= D coordinates; only the first D are used.
 template <typename T, int D, bool BWD, int DA = D>
 __device__ __forceinline__ bool walker_step(cenv<T> p0, Walker<T, DA>& s, uint32_t q, uint32_t key0,
-                                            uint32_t key1, WalkEnd<T>& e)
+                                            uint32_t key1, WalkEnd<T>& e, WorkCount& wc, bool live)
 {
     static_assert(DA >= D, "walker storage narrower than the dimension");
     const T(&x)[D] = reinterpret_cast<const T(&)[D]>(s.x);
     int cls;
-    const T R = distance<T, D>(fresh(p0), x, cls, s.ev);
+    const T R = distance<T, D>(fresh(p0), x, cls, wc, live);
     cenv<T> p = fresh(p0);
     const uint32_t k = s.k;
     if (R < p->eps) {
@@ -544,7 +552,6 @@ __device__ __forceinline__ bool walker_step(cenv<T> p0, Walker<T, DA>& s, uint32
         e.gs = first ? T(0) : s.gfac * s.W1 * g;
         e.S = s.S;
         e.goal_w = (cls == kGoal) ? s.W : T(0);
-        e.ev = s.ev;
         return true;
     }
     if (k + 1 >= p->max_steps) {
@@ -555,7 +562,6 @@ __device__ __forceinline__ bool walker_step(cenv<T> p0, Walker<T, DA>& s, uint32
         e.gs = T(0);
         e.S = T(0);
         e.goal_w = T(0);
-        e.ev = s.ev;
         return true;
     }
     const T R2 = R * R;

@@ -66,8 +66,16 @@ __device__ __forceinline__ void accumulate(double (&a)[nacc(DA)], const WalkEnd<
     a[4 + 2 * DA] += (e.status == kDegenerate) ? 1.0 : 0.0;
     a[5 + 2 * DA] += u * (double)e.S;
     a[6 + 2 * DA] += (double)e.goal_w;
-    a[7 + 2 * DA] += (double)e.ev.sph;
-    a[8 + 2 * DA] += (double)e.ev.box;
+}
+
+// The wave's work tally goes into lane 0's accumulators before the wave sum.
+template <int N>
+__device__ __forceinline__ void add_work(double (&a)[N], int at, const WorkCount& wc)
+{
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        a[at] += (double)wc.sph;
+        a[at + 1] += (double)wc.box;
+    }
 }
 
 // ------------------------------------------------------------------------
@@ -102,9 +110,16 @@ plain_kernel(const EnvP<T>* penv, const T* __restrict__ queries, int64_t n_units
     e.steps = 0;
     e.status = kTruncated;
     e.cls = kOuter;
-    e.ev.sph = e.ev.box = 0;
-    if (active) {
-        while (!walker_step<T, D, BWD>(p, s, q_base + (uint32_t)q, k0, k1, e)) {
+    WorkCount wc{0, 0};
+    // every lane steps until the wave's last walk ends (a finished lane runs
+    // along idle), so the obstacle scans and the work tally stay wave-uniform
+    bool done = !active;
+    while (__any(!done)) {
+        WalkEnd<T> ek;
+        const bool fin = walker_step<T, D, BWD>(p, s, q_base + (uint32_t)q, k0, k1, ek, wc, !done);
+        if (fin && !done) {
+            e = ek;
+            done = true;
         }
     }
 
@@ -112,6 +127,7 @@ plain_kernel(const EnvP<T>* penv, const T* __restrict__ queries, int64_t n_units
 #pragma unroll
     for (int i = 0; i < nacc(D); ++i) a[i] = 0.0;
     if (active) accumulate<T, D>(a, e, s.v0);
+    add_work(a, 7 + 2 * D, wc);
     wave_store<nacc(D)>(a, partials + unit * nacc(D));
 
     if (records != nullptr && active) {
@@ -219,27 +235,32 @@ constexpr int kNAccBatch = nacc(kMaxDim);
 // One walk step of an env of dimension d on the shared 8-wide walker state.
 template <bool BWD>
 __device__ __forceinline__ bool step_any_d(int d, cenv<float> p, Walker<float, kMaxDim>& s, uint32_t q,
-                                           uint32_t k0, uint32_t k1, WalkEnd<float>& e)
+                                           uint32_t k0, uint32_t k1, WalkEnd<float>& e, WorkCount& wc,
+                                           bool live)
 {
     switch (d) {
-    case 2: return walker_step<float, 2, BWD, kMaxDim>(p, s, q, k0, k1, e);
-    case 3: return walker_step<float, 3, BWD, kMaxDim>(p, s, q, k0, k1, e);
-    case 4: return walker_step<float, 4, BWD, kMaxDim>(p, s, q, k0, k1, e);
-    case 5: return walker_step<float, 5, BWD, kMaxDim>(p, s, q, k0, k1, e);
-    case 6: return walker_step<float, 6, BWD, kMaxDim>(p, s, q, k0, k1, e);
-    case 7: return walker_step<float, 7, BWD, kMaxDim>(p, s, q, k0, k1, e);
-    default: return walker_step<float, 8, BWD, kMaxDim>(p, s, q, k0, k1, e);
+    case 2: return walker_step<float, 2, BWD, kMaxDim>(p, s, q, k0, k1, e, wc, live);
+    case 3: return walker_step<float, 3, BWD, kMaxDim>(p, s, q, k0, k1, e, wc, live);
+    case 4: return walker_step<float, 4, BWD, kMaxDim>(p, s, q, k0, k1, e, wc, live);
+    case 5: return walker_step<float, 5, BWD, kMaxDim>(p, s, q, k0, k1, e, wc, live);
+    case 6: return walker_step<float, 6, BWD, kMaxDim>(p, s, q, k0, k1, e, wc, live);
+    case 7: return walker_step<float, 7, BWD, kMaxDim>(p, s, q, k0, k1, e, wc, live);
+    default: return walker_step<float, 8, BWD, kMaxDim>(p, s, q, k0, k1, e, wc, live);
     }
 }
 
+// Gradient sums and sums of squares of a work unit (2 x kMaxDim doubles per
+// lane) live in LDS: they change only when a walk ends, and keeping them out
+// of registers leaves the walk loop without register spills.  Layout per
+// wave: [entry][lane], so a wave's accesses to one entry are contiguous.
+constexpr int kLdsAcc = 2 * kMaxDim;
+
 // One work unit: walks [w_begin, w_end) of one query, with lane refill.  The
-// walker state and accumulator row are 8 wide for every d, so the dimension
-// only selects the step code.  (Keeping the accumulator row in LDS instead of
-// registers measured slower: its read-modify-write runs in every iteration in
-// which any lane of the wave finishes a walk, about half of them.)
+// walker state is 8 wide for every d, so the dimension only selects the step
+// code.  Accumulators other than the gradient ones stay in registers.
 template <bool BWD>
 __device__ __forceinline__ void run_unit(cenv<float> p, CBatch& be, int64_t local, const float* queries,
-                                         uint32_t k0, uint32_t k1, double* out)
+                                         uint32_t k0, uint32_t k1, double* lds, double* out)
 {
     const int lane = threadIdx.x & (kWave - 1);
     const int d = be.d;
@@ -254,9 +275,16 @@ __device__ __forceinline__ void run_unit(cenv<float> p, CBatch& be, int64_t loca
 #pragma unroll
     for (int i = 0; i < kMaxDim; ++i) xq[i] = (i < d) ? qrow[i < d ? i : 0] : 0.0f;
 
-    double a[kNAccBatch];
+    // registers: [0] u, [1] u^2, then steps, truncated, degenerate, u S,
+    // goal weight, sphere and box distances (the nacc layout without the
+    // gradient entries; the last two from the wave's work tally)
+    constexpr int NR = kNAccBatch - kLdsAcc;
+    double a[NR];
 #pragma unroll
-    for (int i = 0; i < kNAccBatch; ++i) a[i] = 0.0;
+    for (int i = 0; i < NR; ++i) a[i] = 0.0;
+    double* g = lds + lane;
+#pragma unroll
+    for (int i = 0; i < kLdsAcc; ++i) g[i * kWave] = 0.0;
 
     Walker<float, kMaxDim> s;
     int64_t next = w_begin + lane;
@@ -264,13 +292,29 @@ __device__ __forceinline__ void run_unit(cenv<float> p, CBatch& be, int64_t loca
     walker_start<float, kMaxDim, kMaxDim>(s, xq, (uint32_t)next);
     int64_t base = w_begin + kWave;
     const uint32_t qi = (uint32_t)ql;
+    WorkCount wc{0, 0};
 
     while (__any(active)) {
         WalkEnd<float> e;
-        bool fin = false;
-        if (active) {
-            fin = step_any_d<BWD>(d, p, s, qi, k0, k1, e);
-            if (fin) accumulate<float, kMaxDim, kMaxDim>(a, e, s.v0);
+        // idle lanes (the unit has no walks left for them) step along
+        bool fin = step_any_d<BWD>(d, p, s, qi, k0, k1, e, wc, active);
+        fin = fin && active;
+        {
+            if (fin) {
+                const double u = (double)e.u;
+                a[0] += u;
+                a[1] += u * u;
+                a[2] += (double)e.steps;
+                a[3] += (e.status == kTruncated) ? 1.0 : 0.0;
+                a[4] += (e.status == kDegenerate) ? 1.0 : 0.0;
+                a[5] += u * (double)e.S;
+                a[6] += (double)e.goal_w;
+                for (int i = 0; i < d; ++i) {
+                    const double gi = (double)(e.gs * s.v0[i]);
+                    g[i * kWave] += gi;
+                    g[(kMaxDim + i) * kWave] += gi * gi;
+                }
+            }
         }
         // lane refill: finished lanes take the unit's next walks in lane order
         const uint64_t m = __ballot(fin);
@@ -288,7 +332,16 @@ __device__ __forceinline__ void run_unit(cenv<float> p, CBatch& be, int64_t loca
             base += __popcll(m);
         }
     }
-    wave_store<kNAccBatch>(a, out);
+    add_work(a, 7, wc);
+    // back to the nacc(kMaxDim) layout for the partial row
+    double row[kNAccBatch];
+    row[0] = a[0];
+    row[1] = a[1];
+#pragma unroll
+    for (int i = 0; i < kLdsAcc; ++i) row[2 + i] = g[i * kWave];
+#pragma unroll
+    for (int i = 2; i < NR; ++i) row[kLdsAcc + i] = a[i];
+    wave_store<kNAccBatch>(row, out);
 }
 
 // 4 waves per SIMD: the register allocator then spills about 100 bytes per lane
@@ -304,6 +357,8 @@ persistent_kernel(const EnvP<float>* envs, const BatchEnv* benv, int n_benv,
                   uint32_t key0, uint32_t key1, const uint64_t* __restrict__ key_add,
                   unsigned* counter, double* __restrict__ partials)
 {
+    __shared__ double lds_acc[kBlock / kWave][kLdsAcc * kWave];
+    double* lds = lds_acc[threadIdx.x / kWave];
     uint32_t k0 = key0, k1 = key1;
     apply_key_add(k0, k1, key_add);
     CBatch* B = (CBatch*)benv;
@@ -324,7 +379,7 @@ persistent_kernel(const EnvP<float>* envs, const BatchEnv* benv, int n_benv,
         }
         CBatch& be = B[lo];
         const cenv<float> p = (cenv<float>)(envs + be.slot);
-        run_unit<BWD>(p, be, (int64_t)u - be.unit_off, queries, k0, k1, partials + (int64_t)u * kNAccBatch);
+        run_unit<BWD>(p, be, (int64_t)u - be.unit_off, queries, k0, k1, lds, partials + (int64_t)u * kNAccBatch);
     }
 }
 
@@ -407,8 +462,8 @@ plan_update(const EnvP<float>* penv, float* __restrict__ x, int64_t n, const flo
 #pragma unroll
         for (int i = 0; i < D; ++i) xs[i] = x[s * D + i];
         int cls;
-        DistCount ev{0u, 0u};
-        const float R = distance<float, D>(p, xs, cls, ev);
+        WorkCount wc{0, 0};
+        const float R = distance<float, D>(p, xs, cls, wc, true);
         if (R < p->eps) {
             status[s] = (cls == kGoal) ? 1 : 2;
         } else {
