@@ -31,6 +31,7 @@ def build():
 class OrDomain(C.Structure):
     _fields_ = [
         ("d", C.c_int),
+        ("has_src", C.c_int), ("src_z", C.c_double * MAXD), ("src_amp", C.c_double), ("c_imp", C.c_double),
         ("n_sph", C.c_int), ("sph_c", C.POINTER(C.c_double)), ("sph_r", C.POINTER(C.c_double)),
         ("n_box", C.c_int), ("box_c", C.POINTER(C.c_double)), ("box_h", C.POINTER(C.c_double)),
         ("has_goal", C.c_int), ("goal_c", C.c_double * MAXD), ("goal_r", C.c_double),
@@ -43,7 +44,7 @@ class OrDomain(C.Structure):
 
 class OrWalk(C.Structure):
     _fields_ = [("u", C.c_double), ("grad", C.c_double * MAXD), ("dlnC_sum", C.c_double),
-                ("goal_w", C.c_double), ("steps", C.c_int), ("status", C.c_int),
+                ("du_dsigma", C.c_double), ("goal_w", C.c_double), ("steps", C.c_int), ("status", C.c_int),
                 ("cls", C.c_int), ("idx", C.c_int)]
 
 
@@ -72,6 +73,13 @@ def lib():
             getattr(L, f).restype = C.c_double
         L.or_hyp0f1.argtypes = [C.c_double, C.c_double]
         L.or_hyp0f1.restype = C.c_double
+        L.or_bessel_k.argtypes = [C.c_double, C.c_double]
+        L.or_bessel_k.restype = C.c_double
+        L.or_yukawa_free.argtypes = [C.c_int, C.c_double, C.c_double]
+        L.or_yukawa_free.restype = C.c_double
+        for f in ("or_ball_green", "or_ball_green_grad", "or_ball_green_dsigma"):
+            getattr(L, f).argtypes = [C.c_int, C.c_double, C.c_double, C.c_double]
+            getattr(L, f).restype = C.c_double
         L.or_walk.argtypes = [C.POINTER(OrDomain), dp, C.c_double, C.c_double, C.c_uint64,
                               u32, u32, u32, C.c_int, C.POINTER(OrWalk)]
         L.or_estimate.argtypes = [C.POINTER(OrDomain), dp, C.c_int64, C.c_int64, C.c_double,
@@ -137,6 +145,13 @@ class Domain:
         for i in range(d):
             D.ak[i] = float(b["ak"][i])
         D.b = float(b["b"])
+        src = scene.get("source")
+        if src is not None:
+            D.has_src = 1
+            for i in range(d):
+                D.src_z[i] = float(src["z"][i])
+            D.src_amp = float(src.get("amp", 1.0))
+            D.c_imp = float(src.get("c_imp", 1.0))
         self.s = D
 
     @property
@@ -189,6 +204,26 @@ def hyp0f1(b, y):
     return lib().or_hyp0f1(float(b), float(y))
 
 
+def bessel_k(nu, z):
+    return lib().or_bessel_k(float(nu), float(z))
+
+
+def yukawa_free(d, sigma, r):
+    return lib().or_yukawa_free(int(d), float(sigma), float(r))
+
+
+def ball_green(d, sigma, r, R):
+    return lib().or_ball_green(int(d), float(sigma), float(r), float(R))
+
+
+def ball_green_grad(d, sigma, r, R):
+    return lib().or_ball_green_grad(int(d), float(sigma), float(r), float(R))
+
+
+def ball_green_dsigma(d, sigma, r, R):
+    return lib().or_ball_green_dsigma(int(d), float(sigma), float(r), float(R))
+
+
 def screening_C(d, sigma, R):
     return lib().or_screening_C(d, float(sigma), float(R))
 
@@ -210,7 +245,7 @@ def walk(scene, x, w, q=0, env=0, sigma=None, eps=None, seed=None, max_steps=DEF
                   scene["eps"] if eps is None else eps, scene["seed"] if seed is None else seed,
                   w, q, env, max_steps, C.byref(r))
     return {"u": r.u, "grad": np.array(r.grad[:dom.d]), "dlnC_sum": r.dlnC_sum,
-            "goal_w": r.goal_w, "steps": r.steps, "status": r.status, "cls": r.cls,
+            "du_dsigma": r.du_dsigma, "goal_w": r.goal_w, "steps": r.steps, "status": r.status, "cls": r.cls,
             "idx": r.idx}
 
 

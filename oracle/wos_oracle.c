@@ -29,6 +29,16 @@
  *   are distances), so d u_hat / d sigma = u_hat * sum_k d ln C(R_k) / d sigma
  *   exactly, with d ln C / d sigma = -(R^2 / 2d) 0F1(;d/2+1;y) / 0F1(;d/2;y);
  *   u is linear in the goal value, so d u_hat / d g_goal = W 1{goal}.
+ *   Point source (Sec. VI and VII: a unit impulse at the goal point z with
+ *   zero boundary data; Sec. IV-A: the |B| f G_c term of u_hat and the
+ *   c_imp grad G_c term of the gradient): with f = amp delta_z the volume
+ *   term of step k is amp G_B(x_k, z) 1{|z - x_k| < R_k}, G_B the Green's
+ *   function of (-Laplacian + sigma) on the ball B(x_k, R_k) with zero data
+ *   on its sphere (the sign that makes u >= 0 peak at the source).  So
+ *       u_hat(x_0) = sum_k W_k amp G_B(|z - x_k|; R_k) 1{.} + W_K g(xbar_K),
+ *       grad_hat u(x_0) = (d / R_0) C1(R_0) u_hat(x_1) v_0
+ *                         + c_imp amp grad_x G_B(x_0, z) 1{|z - x_0| < R_0},
+ *   with u_hat(x_1) the same sum over the walk from x_1 (weights W1_k).
  *
  * Random numbers: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11), key =
  * 64-bit seed, counter = (2k + j, walk, query, env) for step k and block j;
@@ -49,6 +59,9 @@ enum { OR_ABSORBED = 0, OR_DEGENERATE = 1, OR_TRUNCATED = 2 };
 
 typedef struct {
     int d;
+    int has_src;         /* point source amp delta_z */
+    double src_z[OR_MAXD];
+    double src_amp, c_imp;
     int n_sph;
     const double* sph_c; /* n_sph x d */
     const double* sph_r; /* n_sph */
@@ -72,6 +85,7 @@ typedef struct {
     double u;                /* one-point estimate u_hat(x_0) */
     double grad[OR_MAXD];    /* one-point gradient estimate */
     double dlnC_sum;         /* sum over weighted steps of d ln C / d sigma */
+    double du_dsigma;        /* d u_hat / d sigma (u_hat dlnC_sum without a source) */
     double goal_w;           /* W * 1{absorbed on the goal} */
     int steps;               /* distance evaluations made */
     int status;              /* OR_ABSORBED / OR_DEGENERATE / OR_TRUNCATED */
@@ -313,6 +327,103 @@ double or_dlnC_dsigma(int d, double sigma, double R)
 }
 
 /* ------------------------------------------------------------------------ */
+/* Point-source terms: Bessel functions and the Green's function of the ball. */
+/* nu = d/2 - 1.  Free-space fundamental solution of (-Laplacian + sigma):     */
+/*   sigma > 0: Phi(r) = (2 pi)^(-d/2) sigma^(nu/2) r^(-nu) K_nu(sqrt(sigma) r) */
+/*   sigma = 0: Phi(r) = -ln(r) / (2 pi) (d = 2), r^(2-d) / ((d-2) |S^(d-1)|). */
+/* Ball of radius R, source at distance r from the centre, zero data on the   */
+/* sphere (the l = 0 mode):  G_B(r; R) = Phi(r) - Phi(R) p(r) / p(R),          */
+/* p(s) = 0F1(; nu+1; sigma s^2 / 4), the regular radial solution (p = 1 at    */
+/* sigma = 0).  Gradient in the centre point towards the source (the l = 1    */
+/* mode, which vanishes on the sphere and has the free-space singularity):    */
+/*   sigma > 0: (2 pi)^(-d/2) sigma^((nu+1)/2) r^(-nu)                         */
+/*              [K_{nu+1}(sqrt(sigma) r) - K_{nu+1}(sqrt(sigma) R) (r/R)^(nu+1) */
+/*               p1(r) / p1(R)],   p1(s) = 0F1(; nu+2; sigma s^2 / 4),          */
+/*   sigma = 0: (r^(1-d) - r R^(-d)) / |S^(d-1)|.                              */
+/* ------------------------------------------------------------------------ */
+
+/* K_nu(z), z > 0, from its integral representation (DLMF 10.32.9)
+ * K_nu(z) = int_0^inf exp(-z cosh t) cosh(nu t) dt, by the trapezoidal rule
+ * with step 1/16 (the integrand is analytic and decays doubly exponentially,
+ * so the rule converges to rounding).  Terms are summed until they are
+ * negligible and decreasing. */
+double or_bessel_k(double nu, double z)
+{
+    if (!(z > 0.0)) return INFINITY;
+    const double h = 1.0 / 16.0;
+    double sum = 0.5 * exp(-z);
+    for (int j = 1; j < 1000000; ++j) {
+        double t = j * h;
+        sum += exp(-z * cosh(t)) * cosh(nu * t);
+        /* past the maximum of the integrand and below the smallest double */
+        if (z * sinh(t) > nu && -z * cosh(t) + nu * t < -745.0) break;
+    }
+    return h * sum;
+}
+
+static double sphere_area(int d)
+{
+    return 2.0 * pow(OR_PI, 0.5 * d) / tgamma(0.5 * d);
+}
+
+/* Free-space fundamental solution Phi(r). */
+double or_yukawa_free(int d, double sigma, double r)
+{
+    double nu = 0.5 * d - 1.0;
+    if (sigma > 0.0)
+        return pow(2.0 * OR_PI, -0.5 * d) * pow(sigma, 0.5 * nu) * pow(r, -nu) * or_bessel_k(nu, sqrt(sigma) * r);
+    if (d == 2) return -log(r) / (2.0 * OR_PI);
+    return pow(r, 2.0 - d) / ((d - 2.0) * sphere_area(d));
+}
+
+/* G_B(r; R): Green's function of the ball between its centre and a point at
+ * distance r < R. */
+double or_ball_green(int d, double sigma, double r, double R)
+{
+    double nu = 0.5 * d - 1.0;
+    double ratio = or_hyp0f1(nu + 1.0, 0.25 * sigma * r * r) / or_hyp0f1(nu + 1.0, 0.25 * sigma * R * R);
+    return or_yukawa_free(d, sigma, r) - or_yukawa_free(d, sigma, R) * ratio;
+}
+
+/* |grad_x G_B(x, y)| at the centre x, towards y, |y - x| = r < R. */
+double or_ball_green_grad(int d, double sigma, double r, double R)
+{
+    double nu = 0.5 * d - 1.0;
+    if (sigma > 0.0) {
+        double rs = sqrt(sigma);
+        double ratio = pow(r / R, nu + 1.0) * or_hyp0f1(nu + 2.0, 0.25 * sigma * r * r) /
+                       or_hyp0f1(nu + 2.0, 0.25 * sigma * R * R);
+        return pow(2.0 * OR_PI, -0.5 * d) * pow(sigma, 0.5 * (nu + 1.0)) * pow(r, -nu) *
+               (or_bessel_k(nu + 1.0, rs * r) - or_bessel_k(nu + 1.0, rs * R) * ratio);
+    }
+    return (pow(r, 1.0 - d) - r * pow(R, -(double)d)) / sphere_area(d);
+}
+
+/* d Phi(r) / d sigma, sigma > 0: from d/dz (z^-nu K_nu(z)) = -z^-nu K_{nu+1}(z)
+ * (DLMF 10.29.4), (2 pi)^(-d/2) r^(-nu) [nu sigma^(nu/2 - 1) K_nu(z)
+ * - (r / 2) sigma^((nu - 1)/2) K_{nu+1}(z)], z = sqrt(sigma) r. */
+static double yukawa_free_dsigma(int d, double sigma, double r)
+{
+    double nu = 0.5 * d - 1.0, z = sqrt(sigma) * r;
+    return pow(2.0 * OR_PI, -0.5 * d) * pow(r, -nu) *
+           (nu * pow(sigma, 0.5 * nu - 1.0) * or_bessel_k(nu, z) -
+            0.5 * r * pow(sigma, 0.5 * (nu - 1.0)) * or_bessel_k(nu + 1.0, z));
+}
+
+/* d G_B(r; R) / d sigma for sigma > 0 (product and quotient rules on the
+ * definition; d p(s) / d sigma = (s^2 / 4) 0F1(; nu+2; sigma s^2 / 4) / (nu + 1)). */
+double or_ball_green_dsigma(int d, double sigma, double r, double R)
+{
+    double nu = 0.5 * d - 1.0;
+    double pr = or_hyp0f1(nu + 1.0, 0.25 * sigma * r * r), pR = or_hyp0f1(nu + 1.0, 0.25 * sigma * R * R);
+    double dpr = 0.25 * r * r * or_hyp0f1(nu + 2.0, 0.25 * sigma * r * r) / (nu + 1.0);
+    double dpR = 0.25 * R * R * or_hyp0f1(nu + 2.0, 0.25 * sigma * R * R) / (nu + 1.0);
+    double dratio = (dpr * pR - pr * dpR) / (pR * pR);
+    return yukawa_free_dsigma(d, sigma, r) - yukawa_free_dsigma(d, sigma, R) * (pr / pR) -
+           or_yukawa_free(d, sigma, R) * dratio;
+}
+
+/* ------------------------------------------------------------------------ */
 /* One walk (Sec. IV-A recursion, unrolled: u_hat(x_0) = prod_k C(R_k) g).     */
 /* ------------------------------------------------------------------------ */
 void or_walk(const or_domain* D, const double* xq, double sigma, double eps, uint64_t seed,
@@ -323,6 +434,10 @@ void or_walk(const or_domain* D, const double* xq, double sigma, double eps, uin
     double W = 1.0;        /* prod_{i < k} C(R_i): weight of u_hat(x_0)            */
     double W1 = 1.0;       /* prod_{1 <= i < k} C(R_i): weight of u_hat(x_1)        */
     double R0 = 0.0, C1_0 = 0.0, S = 0.0;
+    double src = 0.0;      /* sum_k W_k amp G_B(x_k, z): source part of u_hat(x_0)  */
+    double src1 = 0.0;     /* the same with weights W1_k, k >= 1: of u_hat(x_1)     */
+    double srcS = 0.0;     /* sum_k W_k amp (S_k G_B + d G_B / d sigma)             */
+    double gsrc[OR_MAXD] = {0};
     memcpy(x, xq, sizeof(double) * (size_t)d);
     memset(rec, 0, sizeof(*rec));
     for (int k = 0;; ++k) {
@@ -340,15 +455,33 @@ void or_walk(const or_domain* D, const double* xq, double sigma, double eps, uin
                 return;
             }
             rec->status = OR_ABSORBED;
-            rec->u = W * g;
-            for (int i = 0; i < d; ++i) rec->grad[i] = (d / R0) * C1_0 * (W1 * g) * v0[i];
+            rec->u = W * g + src;
+            for (int i = 0; i < d; ++i)
+                rec->grad[i] = (d / R0) * C1_0 * (W1 * g + src1) * v0[i] + gsrc[i];
             rec->dlnC_sum = S;
+            rec->du_dsigma = W * g * S + srcS;
             rec->goal_w = (cls == OR_GOAL) ? W : 0.0;
             return;
         }
         if (k + 1 >= max_steps) { /* step cap reached: walk contributes zero */
             rec->status = OR_TRUNCATED;
             return;
+        }
+        if (D->has_src) { /* the ball around x_k holds the source: volume term */
+            double r2 = 0.0;
+            for (int i = 0; i < d; ++i) r2 += (D->src_z[i] - x[i]) * (D->src_z[i] - x[i]);
+            double r = sqrt(r2);
+            if (r < R) {
+                double G = D->src_amp * or_ball_green(d, sigma, r, R);
+                src += W * G;
+                if (k > 0) src1 += W1 * G;
+                if (sigma > 0.0) srcS += W * (S * G + D->src_amp * or_ball_green_dsigma(d, sigma, r, R));
+                else srcS = NAN; /* d G_B / d sigma at sigma = 0 is not provided */
+                if (k == 0 && r > 0.0) {
+                    double gm = D->c_imp * D->src_amp * or_ball_green_grad(d, sigma, r, R) / r;
+                    for (int i = 0; i < d; ++i) gsrc[i] = gm * (D->src_z[i] - x[i]);
+                }
+            }
         }
         double C = or_screening_C(d, sigma, R);
         W *= C;
@@ -403,7 +536,7 @@ int or_estimate(const or_domain* D, const double* queries, int64_t Q, int64_t n,
                 sg[i] += r.grad[i];
             }
             ssteps += r.steps;
-            sS += r.u * r.dlnC_sum;
+            sS += r.du_dsigma;
             sgoal += r.goal_w;
             if (r.status == OR_TRUNCATED) ++ntr;
             if (r.status == OR_DEGENERATE) ++ndg;
@@ -474,6 +607,14 @@ int or_plan_step(const or_domain* D, double* x, int64_t S, int64_t n, double sig
         if (R < eps) {
             status[s] = (cls == OR_GOAL) ? 1 : 2;
             continue;
+        }
+        if (D->has_src) { /* a point-source goal is reached within one nominal step */
+            double dz2 = 0.0;
+            for (int i = 0; i < d; ++i) dz2 += (xs[i] - D->src_z[i]) * (xs[i] - D->src_z[i]);
+            if (sqrt(dz2) < s_ub) {
+                status[s] = 1;
+                continue;
+            }
         }
         status[s] = 0;
         /* the walks of start s are keyed by query index s */

@@ -310,6 +310,32 @@ def with_bdata(scene, mode, ak=None, b=0.0):
     return s
 
 
+def with_source(scene, z, amp=1.0, c_imp=1.0, keep_goal=False, g_goal=None):
+    """Copy of ``scene`` with a point source amp * delta_z (Sec. VI: a unit
+    impulse at the goal point).  By default the goal ball is dropped and all
+    boundary data are zero, the paper's point-source formulation; with
+    keep_goal the goal ball and boundary data stay (g_goal overrides the goal
+    value)."""
+    s = dict(scene)
+    s["source"] = {"z": np.asarray(z, dtype=np.float64).copy(), "amp": float(amp), "c_imp": float(c_imp)}
+    if not keep_goal:
+        s["goal_c"], s["goal_r"] = None, None
+        s["bdata"] = _bdata(0, scene["d"], g_goal=0.0, g_obs=0.0, g_outer=0.0)
+    elif g_goal is not None:
+        s["bdata"] = dict(scene["bdata"], g_goal=float(g_goal))
+    return s
+
+
+def scene_ball_source(d, R=1.0, sigma=1.0, eps=1e-4, queries=None, n_walks=4096, seed=0):
+    """Ball of radius R around the origin with a unit source at the centre and
+    zero boundary data: u(x) = G_B(|x|; R), the ball's Green's function."""
+    s = scene_ball(d, R=R, sigma=sigma, eps=eps, queries=queries, n_walks=n_walks, seed=seed)
+    s["bdata"] = _bdata(0, d, g_goal=0.0, g_obs=0.0, g_outer=0.0)
+    s["source"] = {"z": np.zeros(d), "amp": 1.0, "c_imp": 1.0}
+    s["name"] = f"ball_src_d{d}"
+    return s
+
+
 def plane_wave_k(d, sigma, seed=0):
     """A wave vector k with |k|^2 = sigma, direction drawn from the seed."""
     rng = np.random.default_rng(1000 + seed)
