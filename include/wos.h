@@ -114,6 +114,19 @@ typedef struct {
     double b;            /* affine offset */
 } wos_bdata;
 
+/* Point source f = amplitude * delta_z (Sec. VI and VII: a unit impulse at the
+ * goal point, with zero boundary data).  A walk step whose largest empty ball
+ * holds z adds amplitude G_B(x_k, z), weighted by the step's screening
+ * product, where G_B is the Green's function of (-Laplacian + sigma) on that
+ * ball with zero data on its sphere (Sec. IV-A, the |B| f G_c term); the
+ * first step adds c_imp * amplitude * grad_x G_B(x_0, z) to the gradient
+ * estimate (the c_imp grad G_c term; c_imp = 1 is the unbiased weight). */
+typedef struct {
+    const double* z;     /* host, d: the source point (inside Omega) */
+    double amplitude;    /* finite */
+    double c_imp;        /* finite, >= 0 */
+} wos_source;
+
 typedef struct {
     uint32_t flags;     /* WOS_FP32 (default) or WOS_FP64, optionally | WOS_FULL_SCAN */
     uint32_t env_id;    /* counter word 3 of the RNG (default 0) */
@@ -132,12 +145,13 @@ typedef struct {
  * (boxes) the domain also keeps them grouped in clusters of 8 with bounding
  * spheres; the walk kernels skip a cluster that provably holds no nearer
  * obstacle, which changes the work done, never a distance or a walk.
+ * source may be NULL (no volume source, the boundary-data problem).
  * Errors: WOS_EDIM, WOS_EINVAL (NULL out/outer/bdata, non-finite values,
- * negative radii, empty box), WOS_ENOMEM, WOS_EHIP.
+ * negative radii, empty box, bad source), WOS_ENOMEM, WOS_EHIP.
  */
 int wos_create_domain(int d, const wos_spheres* spheres, const wos_boxes* boxes,
                       const wos_ball* goal, const wos_outer* outer, const wos_bdata* bdata,
-                      wos_domain** out);
+                      const wos_source* source, wos_domain** out);
 
 /* wos_destroy_domain -- free a domain (NULL is ignored).  The caller ensures no
  * enqueued work still uses it. */
@@ -173,14 +187,17 @@ int wos_estimate(const wos_domain* dom, const void* queries, int64_t n_queries,
  * as queries), regenerating the forward walks from (seed, walk, query,
  * env_id) instead of storing them:
  *   out_dx[q]   = grad_u[q] * grad_hat u(x_q)              (device, Q x d)
- *   out_dsigma  = sum_q grad_u[q] mean_w[u_hat S]          (device double scalar)
+ *   out_dsigma  = sum_q grad_u[q] mean_w[d u_hat / d sigma] (device double scalar)
  *   out_dg_goal = sum_q grad_u[q] mean_w[W 1{goal}]        (device double scalar)
  *   out_dq      device double Q x 2 or NULL: per query (du/dsigma, du/dg_goal)
- * with S = sum over weighted steps of d ln C(R_k)/d sigma (the walk law does not
- * depend on sigma, so this pathwise derivative is exact), W the product of
- * weights; in the affine / plane-wave modes dg_goal is the sensitivity to a
- * constant added to the data on the goal sphere.
- * Errors: as wos_estimate.
+ * with d u_hat / d sigma = (W g) S, S = sum over weighted steps of
+ * d ln C(R_k)/d sigma (the walk law does not depend on sigma, so this
+ * pathwise derivative is exact), W the product of weights; with a point
+ * source each source term W_k G_B adds W_k (S_k G_B + d G_B / d sigma).  In
+ * the affine / plane-wave modes dg_goal is the sensitivity to a constant
+ * added to the data on the goal sphere.
+ * Errors: as wos_estimate; WOS_ENOTSUP for a point source at sigma = 0 (the
+ * sigma derivative of the Laplace Green's function is not provided).
  */
 int wos_backward(const wos_domain* dom, const void* queries, int64_t n_queries, int64_t n_walks,
                  double sigma, double eps, uint64_t seed, const void* grad_u, void* out_dx,
@@ -214,7 +231,8 @@ int wos_backward(const wos_domain* dom, const void* queries, int64_t n_queries, 
  *   out_dg     device double, n_envs (required with grad_u)
  * Walk identities match wos_estimate / wos_backward called per env with
  * env_id = e, so results agree with those calls up to summation order.
- * Errors: as wos_estimate; WOS_ENOTSUP for WOS_FP64.
+ * Errors: as wos_estimate; WOS_ENOTSUP for WOS_FP64, and with grad_u for an
+ * env with a point source at sigma = 0 (as wos_backward).
  */
 int wos_estimate_batch(const wos_domain* const* envs, int n_envs, const float* queries,
                        const int64_t* q_offsets, const double* sigma, const double* eps,
@@ -281,7 +299,7 @@ int wos_set_autotune_cache(const char* cache_path);
  * d values (cast to the compute type); q_index is the query's RNG index.
  * out_records (host double, n x (d + 7)): [u_hat, grad_hat[d], S, goal_w,
  * steps, status (0 absorbed, 1 degenerate, 2 truncated), class (0 goal,
- * 1 sphere, 2 box, 3 outer)].  Synchronous.
+ * 1 sphere, 2 box, 3 outer), d u_hat / d sigma].  Synchronous.
  */
 int wos_debug_walks(const wos_domain* dom, const double* query, uint32_t q_index, int64_t w0,
                     int64_t n, double sigma, double eps, uint64_t seed, const wos_options* opt,

@@ -60,6 +60,10 @@ class BData(C.Structure):
                 ("g_outer", C.c_double), ("a_or_k", C.POINTER(C.c_double)), ("b", C.c_double)]
 
 
+class Source(C.Structure):
+    _fields_ = [("z", C.POINTER(C.c_double)), ("amplitude", C.c_double), ("c_imp", C.c_double)]
+
+
 class Options(C.Structure):
     _fields_ = [("flags", C.c_uint32), ("env_id", C.c_uint32), ("max_steps", C.c_uint32),
                 ("reserved", C.c_uint32)]
@@ -72,7 +76,7 @@ def _load():
     L = C.CDLL(LIB_PATH)
     vp, i64, u64, u32, dp = C.c_void_p, C.c_int64, C.c_uint64, C.c_uint32, C.POINTER(C.c_double)
     L.wos_create_domain.argtypes = [C.c_int, C.POINTER(Spheres), C.POINTER(Boxes), C.POINTER(Ball),
-                                    C.POINTER(Outer), C.POINTER(BData), C.POINTER(vp)]
+                                    C.POINTER(Outer), C.POINTER(BData), C.POINTER(Source), C.POINTER(vp)]
     L.wos_destroy_domain.argtypes = [vp]
     L.wos_destroy_domain.restype = None
     L.wos_domain_dim.argtypes = [vp]
@@ -179,11 +183,17 @@ class Domain:
         ak = arr(b["ak"], (d,))
         bd = BData(int(b["mode"]), float(b["g_goal"]), float(b["g_obs"]), float(b["g_outer"]),
                    _dp(ak), float(b["b"]))
+        src = None
+        if scene.get("source") is not None:
+            z = arr(scene["source"]["z"], (d,))
+            src = Source(_dp(z), float(scene["source"].get("amp", 1.0)),
+                         float(scene["source"].get("c_imp", 1.0)))
         h = C.c_void_p()
         check(lib.wos_create_domain(d, C.byref(sph), C.byref(box), C.byref(goal) if goal else None,
-                                    C.byref(outer), C.byref(bd), C.byref(h)))
+                                    C.byref(outer), C.byref(bd), C.byref(src) if src else None, C.byref(h)))
         self.handle = h
         self.n_obstacles = ns + nb
+        self.has_source = src is not None
 
     def __del__(self):
         h = getattr(self, "handle", None)

@@ -80,6 +80,9 @@ struct wos_domain {
     // clustered copies of the obstacle tables (see EnvP): one buffer per
     // precision, [sphere rows | sphere bounds | box rows | box bounds]
     int32_t n_cl_sph = 0, n_cl_box = 0;
+    bool has_src = false;  // point source amp delta_z
+    double src_z[kMaxDim] = {0};
+    double src_amp = 0, c_imp = 1;
     float* cl_f = nullptr;
     double* cl_d = nullptr;
     size_t off_sph_bnd = 0, off_box_cl = 0, off_box_bnd = 0;
@@ -174,6 +177,25 @@ int make_env(const wos_domain* D, double sigma, double eps, uint64_t seed, uint3
     for (int i = 0; i < kMaxTerms; ++i) {
         p.cC[i] = (T)(i < nC ? cC[i] : 0.0);
         p.cC1[i] = (T)(i < nC1 ? cC1[i] : 0.0);
+    }
+    if (D->has_src) {
+        // Green's-function constants (see ball_green): nu = d/2 - 1
+        const int d = D->d;
+        const double nu = 0.5 * d - 1.0, pi = 3.14159265358979323846;
+        const double area = 2.0 * std::pow(pi, 0.5 * d) / std::tgamma(0.5 * d);
+        p.has_src = 1;
+        for (int i = 0; i < d; ++i) p.src_z[i] = (T)D->src_z[i];
+        p.src_amp = (T)D->src_amp;
+        p.c_imp = (T)D->c_imp;
+        p.nu = (T)nu;
+        p.sqrt_sigma = (T)std::sqrt(sigma);
+        if (sigma > 0.0) {
+            p.phi_c = (T)(std::pow(2.0 * pi, -0.5 * d) * std::pow(sigma, 0.5 * nu));
+            p.grad_c = (T)(std::pow(2.0 * pi, -0.5 * d) * std::pow(sigma, 0.5 * (nu + 1.0)));
+        } else {
+            p.phi_c = (T)(d == 2 ? 1.0 / (2.0 * pi) : 1.0 / ((d - 2.0) * area));
+            p.grad_c = (T)(1.0 / area);
+        }
     }
     return WOS_OK;
 }
@@ -559,7 +581,7 @@ struct BatchLayout {
 // launch has about units_per_wave units per resident wave; envs are ordered
 // by decreasing unit cost (longest-processing-time first).
 void plan_batch(const wos_domain* const* envs, const int64_t* q_off, int n_envs, const int64_t* n_walks,
-                int q_stride, int force_upw, int force_gm, bool full_scan, BatchLayout& L)
+                int q_stride, int force_upw, int force_gm, bool full_scan, bool src, BatchLayout& L)
 {
     const int block = 256;
     int64_t sumQW = 0, maxM = 0, heavyQ = 0, maxW = 1;
@@ -580,7 +602,7 @@ void plan_batch(const wos_domain* const* envs, const int64_t* q_off, int n_envs,
     Tune t = lookup_tune(heavy_d, maxM, heavyQ);
     if (force_upw > 0) t.units_per_wave = force_upw;
     if (force_gm > 0) t.grid_mult = force_gm;
-    const int resident_blocks = persistent_resident_blocks(true, block);
+    const int resident_blocks = persistent_resident_blocks(true, src, block);
     L.grid = std::max(1, resident_blocks * t.grid_mult);
     const int64_t waves = (int64_t)L.grid * (block / kWave);
     const int64_t target = waves * t.units_per_wave;
@@ -647,11 +669,17 @@ int run_batch(const wos_domain* const* envs, int n_envs, const float* queries, c
     if (bwd && (!out_dx || !out_dsigma || !out_dg))
         return fail(WOS_EINVAL, "out_dx, out_dsigma and out_dg are required with grad_u");
     std::vector<EnvP<float>> hp(n_envs);
-    for (int e = 0; e < n_envs; ++e)
+    bool src = false;
+    for (int e = 0; e < n_envs; ++e) {
         if ((rc = make_env<float>(envs[e], sigma[e], eps[e], seed, (uint32_t)e, o, hp[e]))) return rc;
+        src = src || envs[e]->has_src;
+        if (bwd && envs[e]->has_src && !(sigma[e] > 0.0))
+            return fail(WOS_ENOTSUP, "env %d: the sigma derivative of a point source is provided for sigma > 0 only", e);
+    }
 
     BatchLayout L;
-    plan_batch(envs, q_offsets, n_envs, n_walks, kBatchStride, force_upw, force_gm, (o.flags & WOS_FULL_SCAN) != 0, L);
+    plan_batch(envs, q_offsets, n_envs, n_walks, kBatchStride, force_upw, force_gm, (o.flags & WOS_FULL_SCAN) != 0, src,
+               L);
 
     Scratch S(st);
     // one upload: [EnvP x n_envs][BatchEnv x n_envs]
@@ -670,7 +698,7 @@ int run_batch(const wos_domain* const* envs, int n_envs, const float* queries, c
     const EnvP<float>* d_env = (const EnvP<float>*)d_tab;
     const BatchEnv* d_benv = (const BatchEnv*)(d_tab + env_bytes);
     WOS_HIP(launch_fill_u32(counter, 1, 0u, st), "fill");
-    WOS_HIP(launch_persistent(bwd, L.grid, 256, d_env, d_benv, n_envs, queries, L.total_units,
+    WOS_HIP(launch_persistent(bwd, src, L.grid, 256, d_env, d_benv, n_envs, queries, L.total_units,
                               (uint32_t)seed, (uint32_t)(seed >> 32), nullptr, counter, partials, st),
             "persistent walk kernel");
     WOS_HIP(launch_finalize_batch(bwd, d_benv, n_envs, partials, grad_u, out_u, out_grad, kBatchStride,
@@ -689,7 +717,7 @@ extern "C" {
 const char* wos_last_error(void) { return g_err.c_str(); }
 
 int wos_create_domain(int d, const wos_spheres* spheres, const wos_boxes* boxes, const wos_ball* goal,
-                      const wos_outer* outer, const wos_bdata* bdata, wos_domain** out)
+                      const wos_outer* outer, const wos_bdata* bdata, const wos_source* source, wos_domain** out)
 {
     if (!out) return fail(WOS_EINVAL, "out is NULL");
     *out = nullptr;
@@ -699,6 +727,9 @@ int wos_create_domain(int d, const wos_spheres* spheres, const wos_boxes* boxes,
     if (rc) return rc;
     const int64_t ns = spheres ? spheres->n : 0, nb = boxes ? boxes->n : 0;
     if (bdata->mode < 0 || bdata->mode > 2) return fail(WOS_EINVAL, "unknown boundary-data mode %d", bdata->mode);
+    if (source && (!source->z || !finite_all(source->z, d) || !std::isfinite(source->amplitude) ||
+                   !std::isfinite(source->c_imp) || source->c_imp < 0.0))
+        return fail(WOS_EINVAL, "bad point source (z NULL or non-finite, amplitude non-finite, c_imp < 0)");
     if (bdata->mode != 0 && !bdata->a_or_k) return fail(WOS_EINVAL, "a_or_k is required for mode %d", bdata->mode);
 
     wos_domain* D = new wos_domain();
@@ -742,6 +773,12 @@ int wos_create_domain(int d, const wos_spheres* spheres, const wos_boxes* boxes,
     } else {
         delete D;
         return fail(WOS_EINVAL, "unknown outer kind %d", outer->kind);
+    }
+    if (source) {
+        D->has_src = true;
+        for (int i = 0; i < d; ++i) D->src_z[i] = source->z[i];
+        D->src_amp = source->amplitude;
+        D->c_imp = source->c_imp;
     }
     D->mode = bdata->mode;
     D->g_goal = bdata->g_goal;
@@ -882,6 +919,8 @@ static int estimate_impl(const wos_domain* D, const void* queries, int64_t Q, in
         return fail(WOS_EINVAL, "out_u is required");
     }
     if (Q > 0 && !queries) return fail(WOS_EINVAL, "queries is NULL");
+    if (bwd && D->has_src && !(sigma > 0.0))
+        return fail(WOS_ENOTSUP, "the sigma derivative of a point source is provided for sigma > 0 only");
     const int d = D->d;
     const int32_t chunks = (int32_t)((n_walks + kWave - 1) / kWave);
     Scratch S(st);
@@ -907,7 +946,8 @@ static int estimate_impl(const wos_domain* D, const void* queries, int64_t Q, in
         }
         EnvP<double>* pd;
         if ((rc = S.get(&pd, 1)) || (rc = upload(pd, &p, sizeof(p), st))) return rc;
-        WOS_HIP(launch_plain<double>(d, bwd, pd, (const double*)queries, Q, n_walks, 0, 0, nullptr, partials, nullptr, st),
+        WOS_HIP(launch_plain<double>(d, bwd, D->has_src, pd, (const double*)queries, Q, n_walks, 0, 0, nullptr, partials,
+                                     nullptr, st),
                 "plain walk kernel");
         WOS_HIP(launch_finalize_plain<double>(d, bwd, partials, Q, chunks, n_walks, uo, (double*)out_grad, out_stats,
                                               (const double*)grad_u, (double*)out_dx, out_dq, prod, st),
@@ -930,7 +970,8 @@ static int estimate_impl(const wos_domain* D, const void* queries, int64_t Q, in
         }
         EnvP<float>* pd;
         if ((rc = S.get(&pd, 1)) || (rc = upload(pd, &p, sizeof(p), st))) return rc;
-        WOS_HIP(launch_plain<float>(d, bwd, pd, (const float*)queries, Q, n_walks, 0, 0, nullptr, partials, nullptr, st),
+        WOS_HIP(launch_plain<float>(d, bwd, D->has_src, pd, (const float*)queries, Q, n_walks, 0, 0, nullptr, partials,
+                                    nullptr, st),
                 "plain walk kernel");
         WOS_HIP(launch_finalize_plain<float>(d, bwd, partials, Q, chunks, n_walks, uo, (float*)out_grad, out_stats,
                                              (const float*)grad_u, (float*)out_dx, out_dq, prod, st),
@@ -992,7 +1033,7 @@ int wos_debug_walks(const wos_domain* D, const double* query, uint32_t q_index, 
             if (!rc && e == hipSuccess) e = hipMalloc(&pd, sizeof(p));
             if (!rc && e == hipSuccess) e = hipMemcpy(pd, &p, sizeof(p), hipMemcpyHostToDevice);
             if (!rc && e == hipSuccess)
-                e = launch_plain<double>(d, true, (const EnvP<double>*)pd, (const double*)dq, 1, n, w0, q_index, nullptr,
+                e = launch_plain<double>(d, true, D->has_src, (const EnvP<double>*)pd, (const double*)dq, 1, n, w0, q_index, nullptr,
                                          part, rec, nullptr);
             if (e == hipSuccess) e = hipDeviceSynchronize();
             (void)hipFree(pd);
@@ -1006,7 +1047,7 @@ int wos_debug_walks(const wos_domain* D, const double* query, uint32_t q_index, 
             if (!rc && e == hipSuccess) e = hipMalloc(&pd, sizeof(p));
             if (!rc && e == hipSuccess) e = hipMemcpy(pd, &p, sizeof(p), hipMemcpyHostToDevice);
             if (!rc && e == hipSuccess)
-                e = launch_plain<float>(d, true, (const EnvP<float>*)pd, (const float*)dq, 1, n, w0, q_index, nullptr,
+                e = launch_plain<float>(d, true, D->has_src, (const EnvP<float>*)pd, (const float*)dq, 1, n, w0, q_index, nullptr,
                                         part, rec, nullptr);
             if (e == hipSuccess) e = hipDeviceSynchronize();
             (void)hipFree(pd);
@@ -1100,7 +1141,7 @@ int wos_plan_create(const wos_domain* D, float* x, int64_t n_starts, int64_t n_w
     const int64_t qoff[2] = {0, n_starts};
     const int64_t nw[1] = {n_walks};
     BatchLayout L;
-    plan_batch(envs, qoff, 1, nw, D->d, 0, 0, (o.flags & WOS_FULL_SCAN) != 0, L);
+    plan_batch(envs, qoff, 1, nw, D->d, 0, 0, (o.flags & WOS_FULL_SCAN) != 0, D->has_src, L);
     const int64_t S = n_starts;
     if (e == hipSuccess) e = hipMalloc(&P->u, S * sizeof(float));
     if (e == hipSuccess) e = hipMalloc(&P->grad, S * kBatchStride * sizeof(float));
@@ -1132,7 +1173,7 @@ int wos_plan_create(const wos_domain* D, float* x, int64_t n_starts, int64_t n_w
     // capture [fused forward + backward walks, finalize, update]
     e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        hipError_t e1 = launch_persistent(true, L.grid, 256, P->env, P->benv, 1, x, L.total_units,
+        hipError_t e1 = launch_persistent(true, D->has_src, L.grid, 256, P->env, P->benv, 1, x, L.total_units,
                                           P->henv.key0, P->henv.key1, P->step, P->counter, P->partials, st);
         hipError_t e2 = launch_finalize_batch(true, P->benv, 1, P->partials, P->ubar, P->u, P->grad,
                                               kBatchStride, nullptr, P->dx, P->dsig, P->dg, P->counter, st);
@@ -1225,7 +1266,7 @@ int wos_autotune(int d, int64_t M, int64_t Q, int64_t n_walks, const char* cache
     wos_outer ob{WOS_OUTER_BOX, lo.data(), hi.data(), nullptr, 0};
     wos_bdata bdv{WOS_BDATA_CLASS, 1.0, 0.0, 0.0, nullptr, 0.0};
     wos_domain* D = nullptr;
-    int rc = wos_create_domain(d, &sp, nullptr, &goal, &ob, &bdv, &D);
+    int rc = wos_create_domain(d, &sp, nullptr, &goal, &ob, &bdv, nullptr, &D);
     if (rc) return rc;
     std::vector<float> hq((size_t)Q * kBatchStride, 0.f);
     for (int64_t q = 0; q < Q; ++q)

@@ -63,6 +63,8 @@ struct Math<float> {
     static __device__ __forceinline__ float max(float a, float b) { return __builtin_fmaxf(a, b); }
     static __device__ __forceinline__ float abs(float a) { return __builtin_fabsf(a); }
     static __device__ __forceinline__ float exp(float x) { return __expf(x); }
+    static __device__ __forceinline__ float log(float x) { return __logf(x); }
+    static __device__ __forceinline__ float pow(float x, float y) { return __expf(y * __logf(x)); }
     // Box-Muller radius sqrt(-2 ln u) with ln u = ln 2 * log2 u
     static __device__ __forceinline__ float bm_radius(float u)
     {
@@ -92,6 +94,8 @@ struct Math<double> {
     static __device__ __forceinline__ double max(double a, double b) { return __builtin_fmax(a, b); }
     static __device__ __forceinline__ double abs(double a) { return __builtin_fabs(a); }
     static __device__ __forceinline__ double exp(double x) { return ::exp(x); }
+    static __device__ __forceinline__ double log(double x) { return ::log(x); }
+    static __device__ __forceinline__ double pow(double x, double y) { return ::pow(x, y); }
     static __device__ __forceinline__ double bm_radius(double u) { return ::sqrt(-2.0 * ::log(u)); }
     static __device__ __forceinline__ void sincos_turns(double t, double& s, double& c)
     {
@@ -488,6 +492,103 @@ __device__ __forceinline__ T horner(const C& c, int nt, T y)
 }
 
 // ------------------------------------------------------------------------
+// Point source (Sec. VI: a unit impulse at the goal point with zero boundary
+// data; Sec. IV-A: the volume term of a step whose ball holds the source and
+// the c_imp grad G term of the first-sphere gradient).  nu = d/2 - 1; G_B is
+// the Green's function of (-Laplacian + sigma) on the ball of radius R with
+// zero data on its sphere, between the centre and a point at distance r:
+//   G_B = Phi(r) - Phi(R) p(r) / p(R),  Phi(s) = phi_c s^-nu K_nu(sqrt(sigma) s),
+//   p(s) = 0F1(; nu+1; sigma s^2 / 4);
+// its centre gradient towards the point has length
+//   grad_c r^-nu [K_{nu+1}(sqrt(sigma) r) - K_{nu+1}(sqrt(sigma) R) (r/R)^(nu+1) p1(r) / p1(R)],
+//   p1(s) = 0F1(; nu+2; sigma s^2 / 4);
+// at sigma = 0 both take their Laplace forms.
+// ------------------------------------------------------------------------
+
+// K_nu(z) and K_{nu+1}(z), z > 0, together: the trapezoidal rule on the
+// integral of exp(-z cosh t) cosh(nu t) over t >= 0, with step
+// min(1/4, 1/(2 sqrt(z))) (the integrand's width near 0 shrinks like
+// 1/sqrt(z)), summed until the terms are past their peak and below the
+// precision's rounding.  cosh(nu t) exp(-z cosh t) is formed as
+// (exp(a + nu t) + exp(a - nu t)) / 2, a = -z cosh t, with the exponent capped
+// so that a source closer than about 1e-9 cannot overflow FP32.
+template <typename T>
+__device__ __forceinline__ void bessel_k_pair(T nu, T z, T& k0, T& k1)
+{
+    if (!(z > T(0))) {
+        k0 = k1 = Math<T>::inf();
+        return;
+    }
+    const T tol = sizeof(T) == 4 ? T(1e-8) : T(1e-17);
+    const T cap = T(80);
+    const T h = Math<T>::min(T(0.25), T(0.5) * Math<T>::rsqrt(z));
+    const T e0 = Math<T>::exp(-z);
+    T s0 = T(0.5) * e0, s1 = T(0.5) * e0;
+    for (int j = 1; j < 4096; ++j) {
+        const T t = T(j) * h;
+        const T et = Math<T>::exp(t);
+        const T iet = Math<T>::rcp(et);
+        const T a = -z * T(0.5) * (et + iet);
+        const T u0 = T(0.5) * (Math<T>::exp(Math<T>::min(a + nu * t, cap)) + Math<T>::exp(a - nu * t));
+        const T u1 = T(0.5) * (Math<T>::exp(Math<T>::min(a + (nu + T(1)) * t, cap)) + Math<T>::exp(a - (nu + T(1)) * t));
+        s0 += u0;
+        s1 += u1;
+        if (z * T(0.5) * (et - iet) > nu + T(1) && u1 <= tol * s1) break;
+    }
+    k0 = h * s0;
+    k1 = h * s1;
+}
+
+template <typename T>
+struct SourceTerm {
+    T G;    // G_B(r; R)
+    T gm;   // length of the centre gradient
+    T dG;   // d G_B / d sigma (sigma > 0; NaN at sigma = 0)
+};
+
+template <typename T, int D, bool BWD>
+__device__ __noinline__ SourceTerm<T> ball_green(cenv<T> p, T r, T R)
+{
+    SourceTerm<T> o;
+    if (p->sigma > T(0)) {
+        const T nu = p->nu, sq = p->sqrt_sigma;
+        T Kr, K1r, KR, K1R;
+        bessel_k_pair<T>(nu, sq * r, Kr, K1r);
+        bessel_k_pair<T>(nu, sq * R, KR, K1R);
+        const T yr = p->qsigma * r * r, yR = p->qsigma * R * R;
+        const T pr = horner<T>(p->cC, p->nt_C, yr), pR = horner<T>(p->cC, p->nt_C, yR);
+        const T p1r = horner<T>(p->cC1, p->nt_C1, yr), p1R = horner<T>(p->cC1, p->nt_C1, yR);
+        const T rn = Math<T>::pow(r, -nu), Rn = Math<T>::pow(R, -nu);
+        const T ratio = pr / pR;
+        o.G = p->phi_c * (rn * Kr - Rn * KR * ratio);
+        o.gm = p->grad_c * rn * (K1r - K1R * Math<T>::pow(r / R, nu + T(1)) * (p1r / p1R));
+        if (BWD) {
+            // d Phi(s) / d sigma = phi_c s^-nu [(nu / sigma) K_nu - s / (2 sqrt(sigma)) K_{nu+1}]
+            // d p(s) / d sigma = (s^2 / 4) p1(s) / (nu + 1)
+            const T is = T(1) / p->sigma, ih = T(0.5) / sq;
+            const T dPr = p->phi_c * rn * (nu * is * Kr - r * ih * K1r);
+            const T dPR = p->phi_c * Rn * (nu * is * KR - R * ih * K1R);
+            const T inv = T(1) / (nu + T(1));
+            const T dpr = T(0.25) * r * r * p1r * inv, dpR = T(0.25) * R * R * p1R * inv;
+            const T dratio = (dpr * pR - pr * dpR) / (pR * pR);
+            o.dG = dPr - dPR * ratio - p->phi_c * Rn * KR * dratio;
+        } else {
+            o.dG = T(0);
+        }
+    } else {
+        if (D == 2) {
+            o.G = p->phi_c * Math<T>::log(R / r);
+            o.gm = p->grad_c * (T(1) / r - r / (R * R));
+        } else {
+            o.G = p->phi_c * (Math<T>::pow(r, T(2 - D)) - Math<T>::pow(R, T(2 - D)));
+            o.gm = p->grad_c * (Math<T>::pow(r, T(1 - D)) - r * Math<T>::pow(R, T(-D)));
+        }
+        o.dG = __builtin_nan("");
+    }
+    return o;
+}
+
+// ------------------------------------------------------------------------
 // One walk (Sec. IV-A).  State lives in registers; an iteration makes one
 // distance evaluation and either absorbs (eps-shell, Fig. 2) or applies the
 // step's weight and jumps to a uniform point on the sphere of radius R.
@@ -500,6 +601,10 @@ struct Walker {
     T W1;      // prod_{1 <= i < k} C(R_i): weight of u_hat(x_1)
     T gfac;    // (d / R_0) C1(R_0)
     T S;       // sum_{i < k} d ln C(R_i) / d sigma
+    T src;     // point source: sum_{i < k} W_i amp G_B(x_i): source part of u_hat(x_0)
+    T src1;    // the same with weights W1_i, i >= 1: of u_hat(x_1)
+    T srcS;    // sum_i W_i amp (S_i G_B + d G_B / d sigma)
+    T gs0;     // c_imp amp |grad G_B(x_0, z)| / |z - x_0| (the first ball holds z)
     uint32_t k;
     uint32_t w;
 };
@@ -507,9 +612,12 @@ struct Walker {
 template <typename T>
 struct WalkEnd {
     T u;        // u_hat(x_0)
-    T gs;       // gradient = gs * v0
-    T S;        // d ln u_hat / d sigma
+    T gs;       // gradient = gs * v0 (+ gs0 (z - x_0) with a point source)
+    T S;        // sum of d ln C / d sigma over the weighted steps
     T goal_w;   // W 1{goal}
+    T gs0;      // point source: coefficient of z - x_0 in the gradient
+    T ubd;      // point source: boundary part of u_hat(x_0), W g
+    T srcS;     // point source: source part of d u_hat / d sigma
     uint32_t steps;
     int32_t status, cls;
 };
@@ -525,6 +633,10 @@ __device__ __forceinline__ void walker_start(Walker<T, DA>& s, const T (&xq)[DA]
     s.W1 = T(1);
     s.gfac = T(0);
     s.S = T(0);
+    s.src = T(0);
+    s.src1 = T(0);
+    s.srcS = T(0);
+    s.gs0 = T(0);
     s.k = 0;
     s.w = w;
 }
@@ -532,7 +644,7 @@ __device__ __forceinline__ void walker_start(Walker<T, DA>& s, const T (&xq)[DA]
 // Returns true when the walk ended (e is then filled in).  (key0, key1) is
 // the Philox key of the launch, q the query's index in its environment.  The
 // walker may store DA >= D coordinates; only the first D are used.
-template <typename T, int D, bool BWD, int DA = D>
+template <typename T, int D, bool BWD, int DA = D, bool SRC = false>
 __device__ __forceinline__ bool walker_step(cenv<T> p0, Walker<T, DA>& s, uint32_t q, uint32_t key0,
                                             uint32_t key1, WalkEnd<T>& e, WorkCount& wc, bool live)
 {
@@ -552,6 +664,13 @@ __device__ __forceinline__ bool walker_step(cenv<T> p0, Walker<T, DA>& s, uint32
         e.gs = first ? T(0) : s.gfac * s.W1 * g;
         e.S = s.S;
         e.goal_w = (cls == kGoal) ? s.W : T(0);
+        if (SRC) {
+            e.ubd = e.u;
+            e.u += s.src;
+            e.gs = first ? T(0) : s.gfac * (s.W1 * g + s.src1);
+            e.gs0 = s.gs0;
+            e.srcS = s.srcS;
+        }
         return true;
     }
     if (k + 1 >= p->max_steps) {
@@ -562,7 +681,27 @@ __device__ __forceinline__ bool walker_step(cenv<T> p0, Walker<T, DA>& s, uint32
         e.gs = T(0);
         e.S = T(0);
         e.goal_w = T(0);
+        if (SRC) e.gs0 = e.ubd = e.srcS = T(0);
         return true;
+    }
+    if (SRC && p->has_src) {  // the ball around x_k holds the source: volume term
+        T dz2 = T(0);
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            const T t = p->src_z[i] - x[i];
+            dz2 = Math<T>::fma(t, t, dz2);
+        }
+        if (dz2 < R * R) {
+            const T r = Math<T>::sqrt(dz2);
+            const SourceTerm<T> st = ball_green<T, D, BWD>(p, r, R);
+            p = fresh(p0);
+            const T Ga = p->src_amp * st.G;
+            if (BWD) s.srcS = Math<T>::fma(s.W, Math<T>::fma(s.S, Ga, p->src_amp * st.dG), s.srcS);
+            s.src = Math<T>::fma(s.W, Ga, s.src);
+            if (k > 0) s.src1 = Math<T>::fma(s.W1, Ga, s.src1);
+            else if (r > T(0)) s.gs0 = p->c_imp * p->src_amp * st.gm / r;
+        }
+        p = fresh(p0);
     }
     const T R2 = R * R;
     const T y = p->qsigma * R2;

@@ -47,24 +47,43 @@ __device__ __forceinline__ void wave_store(double (&a)[N], double* out)
     }
 }
 
+// One-point gradient of a finished walk: gs v0, plus gs0 (z - x_0) when a
+// point source lies in the first ball.
+template <typename T, int D, int DA, bool SRC>
+__device__ __forceinline__ T walk_grad(const WalkEnd<T>& e, const T (&v0)[DA], cenv<T> p, const T* xq, int i)
+{
+    T g = e.gs * v0[i];
+    if (SRC) g = Math<T>::fma(e.gs0, p->src_z[i] - xq[i], g);
+    return g;
+}
+
+// d u_hat / d sigma of a finished walk: (W g) S, plus the source part.
+template <typename T, bool SRC>
+__device__ __forceinline__ double walk_dsigma(const WalkEnd<T>& e)
+{
+    if (SRC) return (double)e.ubd * (double)e.S + (double)e.srcS;
+    return (double)e.u * (double)e.S;
+}
+
 // Contribution of one finished walk to an accumulator row laid out for DA
 // coordinates (nacc(DA) entries), of which the first D are in use.
-template <typename T, int D, int DA = D>
-__device__ __forceinline__ void accumulate(double (&a)[nacc(DA)], const WalkEnd<T>& e, const T (&v0)[DA])
+template <typename T, int D, int DA, bool SRC>
+__device__ __forceinline__ void accumulate(double (&a)[nacc(DA)], const WalkEnd<T>& e, const T (&v0)[DA],
+                                           cenv<T> p, const T* xq)
 {
     const double u = (double)e.u;
     a[0] += u;
     a[1] += u * u;
 #pragma unroll
     for (int i = 0; i < D; ++i) {
-        const double g = (double)(e.gs * v0[i]);
+        const double g = (double)walk_grad<T, D, DA, SRC>(e, v0, p, xq, i);
         a[2 + i] += g;
         a[2 + DA + i] += g * g;
     }
     a[2 + 2 * DA] += (double)e.steps;
     a[3 + 2 * DA] += (e.status == kTruncated) ? 1.0 : 0.0;
     a[4 + 2 * DA] += (e.status == kDegenerate) ? 1.0 : 0.0;
-    a[5 + 2 * DA] += u * (double)e.S;
+    a[5 + 2 * DA] += walk_dsigma<T, SRC>(e);
     a[6 + 2 * DA] += (double)e.goal_w;
 }
 
@@ -81,7 +100,7 @@ __device__ __forceinline__ void add_work(double (&a)[N], int at, const WorkCount
 // ------------------------------------------------------------------------
 // Plain kernel.
 // ------------------------------------------------------------------------
-template <typename T, int D, bool BWD>
+template <typename T, int D, bool BWD, bool SRC>
 __global__ void __launch_bounds__(kBlock)
 plain_kernel(const EnvP<T>* penv, const T* __restrict__ queries, int64_t n_units, int32_t chunks,
              int64_t n_walks, int64_t w_base, uint32_t q_base, const uint64_t* __restrict__ key_add,
@@ -116,7 +135,7 @@ plain_kernel(const EnvP<T>* penv, const T* __restrict__ queries, int64_t n_units
     bool done = !active;
     while (__any(!done)) {
         WalkEnd<T> ek;
-        const bool fin = walker_step<T, D, BWD>(p, s, q_base + (uint32_t)q, k0, k1, ek, wc, !done);
+        const bool fin = walker_step<T, D, BWD, D, SRC>(p, s, q_base + (uint32_t)q, k0, k1, ek, wc, !done);
         if (fin && !done) {
             e = ek;
             done = true;
@@ -126,7 +145,7 @@ plain_kernel(const EnvP<T>* penv, const T* __restrict__ queries, int64_t n_units
     double a[nacc(D)];
 #pragma unroll
     for (int i = 0; i < nacc(D); ++i) a[i] = 0.0;
-    if (active) accumulate<T, D>(a, e, s.v0);
+    if (active) accumulate<T, D, D, SRC>(a, e, s.v0, p, xq);
     add_work(a, 7 + 2 * D, wc);
     wave_store<nacc(D)>(a, partials + unit * nacc(D));
 
@@ -134,13 +153,13 @@ plain_kernel(const EnvP<T>* penv, const T* __restrict__ queries, int64_t n_units
         double* r = records + wi * (D + 7);
         r[0] = (double)e.u;
 #pragma unroll
-        for (int i = 0; i < D; ++i) r[1 + i] = (double)(e.gs * s.v0[i]);
+        for (int i = 0; i < D; ++i) r[1 + i] = (double)walk_grad<T, D, D, SRC>(e, s.v0, p, xq, i);
         r[D + 1] = (double)e.S;
         r[D + 2] = (double)e.goal_w;
         r[D + 3] = (double)e.steps;
         r[D + 4] = (double)e.status;
         r[D + 5] = (double)e.cls;
-        r[D + 6] = 0.0;
+        r[D + 6] = walk_dsigma<T, SRC>(e);
     }
 }
 
@@ -233,19 +252,19 @@ typedef __attribute__((address_space(4))) const BatchEnv CBatch;
 constexpr int kNAccBatch = nacc(kMaxDim);
 
 // One walk step of an env of dimension d on the shared 8-wide walker state.
-template <bool BWD>
+template <bool BWD, bool SRC>
 __device__ __forceinline__ bool step_any_d(int d, cenv<float> p, Walker<float, kMaxDim>& s, uint32_t q,
                                            uint32_t k0, uint32_t k1, WalkEnd<float>& e, WorkCount& wc,
                                            bool live)
 {
     switch (d) {
-    case 2: return walker_step<float, 2, BWD, kMaxDim>(p, s, q, k0, k1, e, wc, live);
-    case 3: return walker_step<float, 3, BWD, kMaxDim>(p, s, q, k0, k1, e, wc, live);
-    case 4: return walker_step<float, 4, BWD, kMaxDim>(p, s, q, k0, k1, e, wc, live);
-    case 5: return walker_step<float, 5, BWD, kMaxDim>(p, s, q, k0, k1, e, wc, live);
-    case 6: return walker_step<float, 6, BWD, kMaxDim>(p, s, q, k0, k1, e, wc, live);
-    case 7: return walker_step<float, 7, BWD, kMaxDim>(p, s, q, k0, k1, e, wc, live);
-    default: return walker_step<float, 8, BWD, kMaxDim>(p, s, q, k0, k1, e, wc, live);
+    case 2: return walker_step<float, 2, BWD, kMaxDim, SRC>(p, s, q, k0, k1, e, wc, live);
+    case 3: return walker_step<float, 3, BWD, kMaxDim, SRC>(p, s, q, k0, k1, e, wc, live);
+    case 4: return walker_step<float, 4, BWD, kMaxDim, SRC>(p, s, q, k0, k1, e, wc, live);
+    case 5: return walker_step<float, 5, BWD, kMaxDim, SRC>(p, s, q, k0, k1, e, wc, live);
+    case 6: return walker_step<float, 6, BWD, kMaxDim, SRC>(p, s, q, k0, k1, e, wc, live);
+    case 7: return walker_step<float, 7, BWD, kMaxDim, SRC>(p, s, q, k0, k1, e, wc, live);
+    default: return walker_step<float, 8, BWD, kMaxDim, SRC>(p, s, q, k0, k1, e, wc, live);
     }
 }
 
@@ -258,7 +277,7 @@ constexpr int kLdsAcc = 2 * kMaxDim;
 // One work unit: walks [w_begin, w_end) of one query, with lane refill.  The
 // walker state is 8 wide for every d, so the dimension only selects the step
 // code.  Accumulators other than the gradient ones stay in registers.
-template <bool BWD>
+template <bool BWD, bool SRC>
 __device__ __forceinline__ void run_unit(cenv<float> p, CBatch& be, int64_t local, const float* queries,
                                          uint32_t k0, uint32_t k1, double* lds, double* out)
 {
@@ -297,7 +316,7 @@ __device__ __forceinline__ void run_unit(cenv<float> p, CBatch& be, int64_t loca
     while (__any(active)) {
         WalkEnd<float> e;
         // idle lanes (the unit has no walks left for them) step along
-        bool fin = step_any_d<BWD>(d, p, s, qi, k0, k1, e, wc, active);
+        bool fin = step_any_d<BWD, SRC>(d, p, s, qi, k0, k1, e, wc, active);
         fin = fin && active;
         {
             if (fin) {
@@ -307,10 +326,10 @@ __device__ __forceinline__ void run_unit(cenv<float> p, CBatch& be, int64_t loca
                 a[2] += (double)e.steps;
                 a[3] += (e.status == kTruncated) ? 1.0 : 0.0;
                 a[4] += (e.status == kDegenerate) ? 1.0 : 0.0;
-                a[5] += u * (double)e.S;
+                a[5] += walk_dsigma<float, SRC>(e);
                 a[6] += (double)e.goal_w;
                 for (int i = 0; i < d; ++i) {
-                    const double gi = (double)(e.gs * s.v0[i]);
+                    const double gi = (double)walk_grad<float, kMaxDim, kMaxDim, SRC>(e, s.v0, p, xq, i);
                     g[i * kWave] += gi;
                     g[(kMaxDim + i) * kWave] += gi * gi;
                 }
@@ -350,7 +369,7 @@ __device__ __forceinline__ void run_unit(cenv<float> p, CBatch& be, int64_t loca
 #define WOS_PERSISTENT_MIN_WAVES 4
 #endif
 
-template <bool BWD>
+template <bool BWD, bool SRC>
 __global__ void __launch_bounds__(kBlock, WOS_PERSISTENT_MIN_WAVES)
 persistent_kernel(const EnvP<float>* envs, const BatchEnv* benv, int n_benv,
                   const float* __restrict__ queries, int64_t total_units,
@@ -379,7 +398,7 @@ persistent_kernel(const EnvP<float>* envs, const BatchEnv* benv, int n_benv,
         }
         CBatch& be = B[lo];
         const cenv<float> p = (cenv<float>)(envs + be.slot);
-        run_unit<BWD>(p, be, (int64_t)u - be.unit_off, queries, k0, k1, lds, partials + (int64_t)u * kNAccBatch);
+        run_unit<BWD, SRC>(p, be, (int64_t)u - be.unit_off, queries, k0, k1, lds, partials + (int64_t)u * kNAccBatch);
     }
 }
 
@@ -464,8 +483,15 @@ plan_update(const EnvP<float>* penv, float* __restrict__ x, int64_t n, const flo
         int cls;
         WorkCount wc{0, 0};
         const float R = distance<float, D>(p, xs, cls, wc, true);
+        float dz2 = 0.0f;
+        if (p->has_src) {
+#pragma unroll
+            for (int i = 0; i < D; ++i) dz2 = Math<float>::fma(xs[i] - p->src_z[i], xs[i] - p->src_z[i], dz2);
+        }
         if (R < p->eps) {
             status[s] = (cls == kGoal) ? 1 : 2;
+        } else if (p->has_src && dz2 < s_ub * s_ub) {
+            status[s] = 1;  // a point-source goal is reached within one nominal step
         } else {
             status[s] = 0;
             float g[D];
@@ -508,8 +534,17 @@ inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1)
 // ------------------------------------------------------------------------
 // Launchers.
 // ------------------------------------------------------------------------
+template <typename T, int D, bool BWD, bool SRC>
+static void plain_go(unsigned grid, const EnvP<T>* p, const T* queries, int64_t units, int32_t chunks,
+                     int64_t n_walks, int64_t w_base, uint32_t q_base, const uint64_t* key_add, double* partials,
+                     double* records, hipStream_t st)
+{
+    hipLaunchKernelGGL((plain_kernel<T, D, BWD, SRC>), dim3(grid), dim3(kBlock), 0, st, p, queries, units, chunks,
+                       n_walks, w_base, q_base, key_add, partials, records);
+}
+
 template <typename T, int D>
-static hipError_t plain_d(bool bwd, const EnvP<T>* p, const T* queries, int64_t n_q, int64_t n_walks,
+static hipError_t plain_d(bool bwd, bool src, const EnvP<T>* p, const T* queries, int64_t n_q, int64_t n_walks,
                           int64_t w_base, uint32_t q_base, const uint64_t* key_add, double* partials,
                           double* records, hipStream_t st)
 {
@@ -517,28 +552,30 @@ static hipError_t plain_d(bool bwd, const EnvP<T>* p, const T* queries, int64_t 
     const int64_t units = n_q * chunks;
     if (units == 0) return hipSuccess;
     const unsigned grid = blocks_for(units, kBlock / kWave);
-    if (bwd)
-        hipLaunchKernelGGL((plain_kernel<T, D, true>), dim3(grid), dim3(kBlock), 0, st, p, queries,
-                           units, chunks, n_walks, w_base, q_base, key_add, partials, records);
+    if (bwd && src)
+        plain_go<T, D, true, true>(grid, p, queries, units, chunks, n_walks, w_base, q_base, key_add, partials, records, st);
+    else if (bwd)
+        plain_go<T, D, true, false>(grid, p, queries, units, chunks, n_walks, w_base, q_base, key_add, partials, records, st);
+    else if (src)
+        plain_go<T, D, false, true>(grid, p, queries, units, chunks, n_walks, w_base, q_base, key_add, partials, records, st);
     else
-        hipLaunchKernelGGL((plain_kernel<T, D, false>), dim3(grid), dim3(kBlock), 0, st, p, queries,
-                           units, chunks, n_walks, w_base, q_base, key_add, partials, records);
+        plain_go<T, D, false, false>(grid, p, queries, units, chunks, n_walks, w_base, q_base, key_add, partials, records, st);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_plain(int d, bool bwd, const EnvP<T>* p, const T* queries, int64_t n_q,
+hipError_t launch_plain(int d, bool bwd, bool src, const EnvP<T>* p, const T* queries, int64_t n_q,
                         int64_t n_walks, int64_t w_base, uint32_t q_base, const uint64_t* key_add,
                         double* partials, double* records, hipStream_t st)
 {
     switch (d) {
-    case 2: return plain_d<T, 2>(bwd, p, queries, n_q, n_walks, w_base, q_base, key_add, partials, records, st);
-    case 3: return plain_d<T, 3>(bwd, p, queries, n_q, n_walks, w_base, q_base, key_add, partials, records, st);
-    case 4: return plain_d<T, 4>(bwd, p, queries, n_q, n_walks, w_base, q_base, key_add, partials, records, st);
-    case 5: return plain_d<T, 5>(bwd, p, queries, n_q, n_walks, w_base, q_base, key_add, partials, records, st);
-    case 6: return plain_d<T, 6>(bwd, p, queries, n_q, n_walks, w_base, q_base, key_add, partials, records, st);
-    case 7: return plain_d<T, 7>(bwd, p, queries, n_q, n_walks, w_base, q_base, key_add, partials, records, st);
-    case 8: return plain_d<T, 8>(bwd, p, queries, n_q, n_walks, w_base, q_base, key_add, partials, records, st);
+    case 2: return plain_d<T, 2>(bwd, src, p, queries, n_q, n_walks, w_base, q_base, key_add, partials, records, st);
+    case 3: return plain_d<T, 3>(bwd, src, p, queries, n_q, n_walks, w_base, q_base, key_add, partials, records, st);
+    case 4: return plain_d<T, 4>(bwd, src, p, queries, n_q, n_walks, w_base, q_base, key_add, partials, records, st);
+    case 5: return plain_d<T, 5>(bwd, src, p, queries, n_q, n_walks, w_base, q_base, key_add, partials, records, st);
+    case 6: return plain_d<T, 6>(bwd, src, p, queries, n_q, n_walks, w_base, q_base, key_add, partials, records, st);
+    case 7: return plain_d<T, 7>(bwd, src, p, queries, n_q, n_walks, w_base, q_base, key_add, partials, records, st);
+    case 8: return plain_d<T, 8>(bwd, src, p, queries, n_q, n_walks, w_base, q_base, key_add, partials, records, st);
     default: return hipErrorInvalidValue;
     }
 }
@@ -577,9 +614,9 @@ hipError_t launch_finalize_plain(int d, bool bwd, const double* partials, int64_
     }
 }
 
-template hipError_t launch_plain<float>(int, bool, const EnvP<float>*, const float*, int64_t, int64_t,
+template hipError_t launch_plain<float>(int, bool, bool, const EnvP<float>*, const float*, int64_t, int64_t,
                                         int64_t, uint32_t, const uint64_t*, double*, double*, hipStream_t);
-template hipError_t launch_plain<double>(int, bool, const EnvP<double>*, const double*, int64_t, int64_t,
+template hipError_t launch_plain<double>(int, bool, bool, const EnvP<double>*, const double*, int64_t, int64_t,
                                          int64_t, uint32_t, const uint64_t*, double*, double*, hipStream_t);
 template hipError_t launch_finalize_plain<float>(int, bool, const double*, int64_t, int32_t, int64_t, float*,
                                                  float*, double*, const float*, float*, double*, double*,
@@ -594,27 +631,41 @@ hipError_t launch_reduce_pairs(const double* prod, int64_t n, double* out0, doub
     return hipGetLastError();
 }
 
-hipError_t launch_persistent(bool bwd, int grid, int block, const EnvP<float>* envs, const BatchEnv* benv,
-                             int n_benv, const float* queries, int64_t total_units,
+template <bool BWD, bool SRC>
+static void persistent_go(int grid, int block, const EnvP<float>* envs, const BatchEnv* benv, int n_benv,
+                          const float* queries, int64_t total_units, uint32_t key0, uint32_t key1,
+                          const uint64_t* key_add, unsigned* counter, double* partials, hipStream_t st)
+{
+    hipLaunchKernelGGL((persistent_kernel<BWD, SRC>), dim3(grid), dim3(block), 0, st, envs, benv, n_benv, queries,
+                       total_units, key0, key1, key_add, counter, partials);
+}
+
+hipError_t launch_persistent(bool bwd, bool src, int grid, int block, const EnvP<float>* envs,
+                             const BatchEnv* benv, int n_benv, const float* queries, int64_t total_units,
                              uint32_t key0, uint32_t key1, const uint64_t* key_add, unsigned* counter,
                              double* partials, hipStream_t st)
 {
     if (total_units == 0) return hipSuccess;
     if (block != kBlock) return hipErrorInvalidValue;
-    if (bwd)
-        hipLaunchKernelGGL(persistent_kernel<true>, dim3(grid), dim3(block), 0, st, envs, benv, n_benv,
-                           queries, total_units, key0, key1, key_add, counter, partials);
+    if (bwd && src)
+        persistent_go<true, true>(grid, block, envs, benv, n_benv, queries, total_units, key0, key1, key_add, counter, partials, st);
+    else if (bwd)
+        persistent_go<true, false>(grid, block, envs, benv, n_benv, queries, total_units, key0, key1, key_add, counter, partials, st);
+    else if (src)
+        persistent_go<false, true>(grid, block, envs, benv, n_benv, queries, total_units, key0, key1, key_add, counter, partials, st);
     else
-        hipLaunchKernelGGL(persistent_kernel<false>, dim3(grid), dim3(block), 0, st, envs, benv, n_benv,
-                           queries, total_units, key0, key1, key_add, counter, partials);
+        persistent_go<false, false>(grid, block, envs, benv, n_benv, queries, total_units, key0, key1, key_add, counter, partials, st);
     return hipGetLastError();
 }
 
-int persistent_resident_blocks(bool bwd, int block)
+int persistent_resident_blocks(bool bwd, bool src, int block)
 {
     int per_cu = 0;
-    hipError_t e = bwd ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persistent_kernel<true>, block, 0)
-                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persistent_kernel<false>, block, 0);
+    hipError_t e;
+    if (bwd && src) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persistent_kernel<true, true>, block, 0);
+    else if (bwd) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persistent_kernel<true, false>, block, 0);
+    else if (src) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persistent_kernel<false, true>, block, 0);
+    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persistent_kernel<false, false>, block, 0);
     if (e != hipSuccess || per_cu < 1) per_cu = 1;
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess) return per_cu;

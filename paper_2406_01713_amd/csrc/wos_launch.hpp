@@ -8,9 +8,10 @@
 namespace wos {
 
 // Plain walk kernel: one walk per lane, one wave per (query, 64-walk chunk),
-// no refill.  Writes one partial-sum row per wave.  p is a device pointer.
+// no refill.  Writes one partial-sum row per wave.  p is a device pointer;
+// src selects the variant with point-source terms.
 template <typename T>
-hipError_t launch_plain(int d, bool bwd, const EnvP<T>* p, const T* queries, int64_t n_q,
+hipError_t launch_plain(int d, bool bwd, bool src, const EnvP<T>* p, const T* queries, int64_t n_q,
                         int64_t n_walks, int64_t w_base, uint32_t q_base,
                         const uint64_t* key_add, double* partials, double* records,
                         hipStream_t st);
@@ -28,15 +29,16 @@ hipError_t launch_reduce_pairs(const double* prod, int64_t n, double* out0, doub
                                hipStream_t st);
 
 // Persistent ragged-batch kernel (FP32): grid of resident waves pulling work
-// units from *counter; refills lanes with the next walk of the unit.
-hipError_t launch_persistent(bool bwd, int grid, int block, const EnvP<float>* envs,
+// units from *counter; refills lanes with the next walk of the unit.  src
+// selects the variant with point-source terms (any env of the batch).
+hipError_t launch_persistent(bool bwd, bool src, int grid, int block, const EnvP<float>* envs,
                              const BatchEnv* benv, int n_benv, const float* queries,
                              int64_t total_units, uint32_t key0, uint32_t key1,
                              const uint64_t* key_add, unsigned* counter, double* partials,
                              hipStream_t st);
 
 // Resident waves of the persistent kernel for a block size (occupancy x CUs).
-int persistent_resident_blocks(bool bwd, int block);
+int persistent_resident_blocks(bool bwd, bool src, int block);
 
 // Outputs of a batched launch; one block per env; also resets *counter.
 hipError_t launch_finalize_batch(bool bwd, const BatchEnv* benv, int n_benv,

@@ -58,6 +58,13 @@ struct EnvP {
     T sigma, eps, qsigma;      // qsigma = sigma / 4
     T cC[kMaxTerms];           // c_k = 1 / ((d/2)_k k!)
     T cC1[kMaxTerms];          // c_k = 1 / ((d/2 + 1)_k k!)
+    // point source amp delta_z (has_src 0: none)
+    int32_t has_src, pad_src;
+    T src_z[kMaxDim];
+    T src_amp, c_imp;
+    T nu, sqrt_sigma;
+    T phi_c;                   // sigma > 0: (2 pi)^(-d/2) sigma^(nu/2); sigma = 0: the Laplace constant
+    T grad_c;                  // sigma > 0: (2 pi)^(-d/2) sigma^((nu+1)/2); sigma = 0: 1 / |S^(d-1)|
 };
 
 // Work decomposition of one environment inside a batched launch.

@@ -54,12 +54,12 @@ def test_create_domain_rejects_bad_dimension(B):
     o, keep = _outer(B, 8)
     bd = _bdata(B)
     for d in (0, 1, 9, 100):
-        rc = B.lib.wos_create_domain(d, None, None, None, C.byref(o), C.byref(bd), C.byref(h))
+        rc = B.lib.wos_create_domain(d, None, None, None, C.byref(o), C.byref(bd), None, C.byref(h))
         assert rc == B.WOS_EDIM
         assert b"outside" in B.lib.wos_last_error()
-    assert B.lib.wos_create_domain(3, None, None, None, None, C.byref(bd), C.byref(h)) == B.WOS_EINVAL
-    assert B.lib.wos_create_domain(3, None, None, None, C.byref(o), None, C.byref(h)) == B.WOS_EINVAL
-    assert B.lib.wos_create_domain(3, None, None, None, C.byref(o), C.byref(bd), None) == B.WOS_EINVAL
+    assert B.lib.wos_create_domain(3, None, None, None, None, C.byref(bd), None, C.byref(h)) == B.WOS_EINVAL
+    assert B.lib.wos_create_domain(3, None, None, None, C.byref(o), None, None, C.byref(h)) == B.WOS_EINVAL
+    assert B.lib.wos_create_domain(3, None, None, None, C.byref(o), C.byref(bd), None, None) == B.WOS_EINVAL
 
 
 def test_create_domain_rejects_bad_obstacles(B):
@@ -70,19 +70,19 @@ def test_create_domain_rejects_bad_obstacles(B):
     c = np.zeros((1, d))
     r = np.array([-0.5])
     sp = B.Spheres(1, c.ctypes.data_as(C.POINTER(C.c_double)), r.ctypes.data_as(C.POINTER(C.c_double)))
-    assert B.lib.wos_create_domain(d, C.byref(sp), None, None, C.byref(o), C.byref(bd), C.byref(h)) == B.WOS_EINVAL
+    assert B.lib.wos_create_domain(d, C.byref(sp), None, None, C.byref(o), C.byref(bd), None, C.byref(h)) == B.WOS_EINVAL
     r2 = np.array([np.nan])
     sp2 = B.Spheres(1, c.ctypes.data_as(C.POINTER(C.c_double)), r2.ctypes.data_as(C.POINTER(C.c_double)))
-    assert B.lib.wos_create_domain(d, C.byref(sp2), None, None, C.byref(o), C.byref(bd), C.byref(h)) == B.WOS_EINVAL
+    assert B.lib.wos_create_domain(d, C.byref(sp2), None, None, C.byref(o), C.byref(bd), None, C.byref(h)) == B.WOS_EINVAL
     sp3 = B.Spheres(1, None, None)
-    assert B.lib.wos_create_domain(d, C.byref(sp3), None, None, C.byref(o), C.byref(bd), C.byref(h)) == B.WOS_EINVAL
+    assert B.lib.wos_create_domain(d, C.byref(sp3), None, None, C.byref(o), C.byref(bd), None, C.byref(h)) == B.WOS_EINVAL
     bad = B.BData(7, 1.0, 0.0, 0.0, None, 0.0)
-    assert B.lib.wos_create_domain(d, None, None, None, C.byref(o), C.byref(bad), C.byref(h)) == B.WOS_EINVAL
+    assert B.lib.wos_create_domain(d, None, None, None, C.byref(o), C.byref(bad), None, C.byref(h)) == B.WOS_EINVAL
     lo = np.array([1.0, -1.0])
     hi = np.array([-1.0, 1.0])
     ob = B.Outer(B.WOS_OUTER_BOX, lo.ctypes.data_as(C.POINTER(C.c_double)),
                  hi.ctypes.data_as(C.POINTER(C.c_double)), None, 0.0)
-    assert B.lib.wos_create_domain(d, None, None, None, C.byref(ob), C.byref(bd), C.byref(h)) == B.WOS_EINVAL
+    assert B.lib.wos_create_domain(d, None, None, None, C.byref(ob), C.byref(bd), None, C.byref(h)) == B.WOS_EINVAL
 
 
 def test_calls_reject_null_handles(B):
@@ -111,3 +111,19 @@ def test_product_path_imports_no_oracle():
                 for pat in (r"^\s*(from|import)\s+oracle\b", r"wos_oracle", r"libwos_oracle",
                             r"#include\s+[<\"].*oracle"):
                     assert not re.search(pat, src, flags=re.M), (f, pat)
+
+
+def test_create_domain_rejects_bad_source(B):
+    d = 3
+    h = C.c_void_p()
+    o, keep = _outer(B, d)
+    bd = _bdata(B)
+    zn = np.array([0.0, np.nan, 0.0])
+    z0 = np.zeros(d)
+    for src in (B.Source(zn.ctypes.data_as(C.POINTER(C.c_double)), 1.0, 1.0),
+                B.Source(None, 1.0, 1.0),
+                B.Source(z0.ctypes.data_as(C.POINTER(C.c_double)), 1.0, -1.0),
+                B.Source(z0.ctypes.data_as(C.POINTER(C.c_double)), np.inf, 1.0)):
+        rc = B.lib.wos_create_domain(d, None, None, None, C.byref(o), C.byref(bd), C.byref(src), C.byref(h))
+        assert rc == B.WOS_EINVAL
+        assert b"source" in B.lib.wos_last_error()

@@ -1,0 +1,189 @@
+"""GPU parity of the point-source formulation (a unit impulse at the goal
+point with zero boundary data, Sec. VI-VII; the volume and gradient terms of
+Sec. IV-A) against the FP64 oracle on identical Philox streams: per-walk
+records, per-query means within 4 SE where the variance is finite (d <= 3),
+the exact Green's function of a ball, batched vs plain paths, the sigma
+derivative and the planning loop."""
+import numpy as np
+import pytest
+
+from paper_2406_01713_amd import scenes as S
+from tests.test_gpu_parity import assert_within_4se, dev, gpu_backward, gpu_batch, gpu_estimate
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2406_01713_amd import binding
+    return binding
+
+
+def src_c3(nq, nw, seed=0):
+    """7-D C3 geometry with the source at the goal point and the queries
+    nearest the goal on each segment (so that walks meet the source)."""
+    base = S.scene_c3(n_walks=nw, seed=seed)
+    s = S.with_source(base, base["goal_c"])
+    s["queries"] = base["queries"][31::32][:nq]
+    return s
+
+
+def src_c1(nq, nw, seed=0):
+    """The 2-D RR configuration space with the source at the goal point and
+    clear queries 0.3 from it."""
+    base = S.scene_c1(n_walks=nw, seed=seed)
+    s = S.with_source(base, base["goal_c"])
+    th = np.linspace(0.0, 2 * np.pi, 32, endpoint=False)
+    ring = base["goal_c"] + 0.3 * np.stack([np.cos(th), np.sin(th)], axis=1)
+    s["queries"] = ring[S.clear_mask(ring, s, 0.02)][:nq]
+    assert len(s["queries"]) == nq
+    return s
+
+
+def ball3(nw, sigma=2.0, seed=0):
+    q = np.array([[0.3, 0.0, 0.0], [-0.4, 0.3, 0.2]])
+    return S.scene_ball_source(3, R=1.0, sigma=sigma, queries=q, n_walks=nw, seed=seed)
+
+
+@pytest.mark.parametrize("fp64", [True, False])
+@pytest.mark.parametrize("which", ["c3", "c1", "ball3"])
+def test_source_walk_level_parity(B, oracle, which, fp64):
+    s = {"c3": lambda: src_c3(2, 256), "c1": lambda: src_c1(4, 128), "ball3": lambda: ball3(128)}[which]()
+    dom = B.Domain(s)
+    odom = oracle.Domain(s)
+    d = s["d"]
+    n = s["n_walks"]
+    tol = 1e-9 if fp64 else 2e-4
+    same = hits = 0
+    for qi, x in enumerate(s["queries"]):
+        rec = B.wos_debug_walks(dom, x, qi, 0, n, s["sigma"], s["eps"], s["seed"], B.options(fp64))
+        for w in range(n):
+            r = oracle.walk(s, x, w, qi, dom=odom)
+            if int(rec[w, d + 3]) != r["steps"]:
+                continue
+            same += 1
+            hits += r["u"] != 0.0
+            scale = max(1.0, abs(r["u"]))
+            assert abs(rec[w, 0] - r["u"]) <= tol * scale, (qi, w, rec[w, 0], r["u"])
+            gs = max(1.0, np.abs(r["grad"]).max())
+            assert np.allclose(rec[w, 1:1 + d], r["grad"], rtol=10 * tol, atol=10 * tol * gs), (qi, w)
+            assert abs(rec[w, d + 6] - r["du_dsigma"]) <= 10 * tol * max(1.0, abs(r["du_dsigma"])), (qi, w)
+            assert int(rec[w, d + 4]) == r["status"]
+    total = n * len(s["queries"])
+    assert same / total >= (0.97 if fp64 else 0.80), same / total
+    assert hits >= 0.05 * total, hits  # the source contributes on many walks
+
+
+@pytest.mark.parametrize("which", ["c1", "ball3"])
+def test_source_fp32_estimate_vs_oracle(B, oracle, which):
+    """d <= 3 (finite variance): FP32 plain means within 4 SE of the oracle."""
+    s = src_c1(8, 4096) if which == "c1" else ball3(8192)
+    u, g, st = gpu_estimate(B, s)
+    uc, gc, stc = oracle.estimate(s)
+    assert_within_4se(u, g, uc, gc, stc, s["d"])
+
+
+def test_source_ball_exact_green_function(B, oracle):
+    """Ball with a central unit source: u(x) = G_B(|x|; 1) at 2^20 walks
+    (FP64 GPU), gradient = its radial derivative."""
+    s = ball3(1 << 20, sigma=2.0, seed=5)
+    u, g, st = gpu_estimate(B, s, fp64=True)
+    for q, x in enumerate(s["queries"]):
+        r = np.linalg.norm(x)
+        exact = oracle.ball_green(3, 2.0, r, 1.0)
+        assert abs(u[q] - exact) <= 4 * st[q, 0] + 1e-12, (q, u[q], exact)
+        h = 1e-6
+        dr = (oracle.ball_green(3, 2.0, r + h, 1.0) - oracle.ball_green(3, 2.0, r - h, 1.0)) / (2 * h)
+        assert np.all(np.abs(g[q] - dr * x / r) <= 4 * st[q, 1:4] + 1e-12), (q, g[q], dr * x / r)
+
+
+def test_source_batch_matches_plain(B):
+    """The persistent kernel's source variant over a batch that mixes envs
+    with and without a source reproduces per-env plain calls."""
+    e5 = S.scene_c4_env(5, n_walks=512, seed=7, q_cap=8)
+    envs = [src_c1(6, 512, seed=7), ball3(512, seed=7), S.with_source(e5, e5["goal_c"]),
+            S.scene_c4_env(2, n_walks=512, seed=7, q_cap=8)]
+    for s in envs:
+        s["seed"] = 7
+    n_walks, seed = 512, 7
+    rng = np.random.default_rng(4)
+    Qt = sum(len(e["queries"]) for e in envs)
+    ubar = rng.normal(size=Qt).astype(np.float32)
+    out = gpu_batch(B, envs, n_walks, seed, ubar=ubar)
+    off = out["off"]
+    for e, s in enumerate(envs):
+        d = s["d"]
+        sl = slice(off[e], off[e + 1])
+        u, g, st = gpu_estimate(B, s, n_walks=n_walks, seed=seed, env_id=e)
+        assert np.allclose(out["u"][sl], u, rtol=2e-5, atol=1e-7), e
+        assert np.allclose(out["g"][sl, :d], g, rtol=2e-5, atol=1e-6), e
+        assert np.allclose(out["st"][sl, 9], st[:, d + 1], rtol=1e-12)
+        dx, ds, dg, dq = gpu_backward(B, s, ubar[sl], n_walks=n_walks, seed=seed, env_id=e)
+        assert np.allclose(out["dx"][sl, :d], dx, rtol=2e-5, atol=1e-6), e
+        assert out["ds"][e] == pytest.approx(ds, rel=1e-4, abs=1e-8)
+        assert out["dg"][e] == pytest.approx(dg, rel=1e-4, abs=1e-8)
+
+
+def test_source_backward_fp64_vs_oracle(B, oracle):
+    s = src_c3(4, 512, seed=8)
+    rng = np.random.default_rng(1)
+    ubar = rng.normal(size=4)
+    dx, ds, dg, dq = gpu_backward(B, s, ubar, fp64=True)
+    _, _, stc, dqc = oracle.estimate(s, dq=True)
+    dxc, dsc, dgc = oracle.backward(s, ubar)
+    d = s["d"]
+    assert np.all(np.abs(dx - dxc) <= 4 * np.abs(ubar)[:, None] * stc[:, 1:1 + d] + 1e-9)
+    assert np.allclose(dq, dqc, rtol=2e-3, atol=1e-9)
+    assert ds == pytest.approx(dsc, rel=5e-3, abs=1e-9)
+
+
+def test_source_backward_rejects_sigma_zero(B):
+    import torch
+    s = ball3(64, sigma=0.0)
+    dom = B.Domain(s)
+    q = dev(s["queries"], torch.float32)
+    dx = torch.empty_like(q)
+    ds = torch.empty(1, dtype=torch.float64, device="cuda")
+    dg = torch.empty(1, dtype=torch.float64, device="cuda")
+    with pytest.raises(B.WosError) as ei:
+        B.wos_backward(dom, q, 64, 0.0, s["eps"], 0, dev(np.ones(2), torch.float32), dx, ds, dg, None)
+    assert ei.value.code == B.WOS_ENOTSUP
+    # the forward is defined at sigma = 0
+    u, g, st = gpu_estimate(B, s)
+    assert np.all(np.isfinite(u)) and np.all(u > 0)
+
+
+def test_source_plan_matches_oracle_and_arrives(B, oracle):
+    """Planning towards a point source at the goal point: the captured graph
+    follows the oracle's steps, and starts near the source arrive."""
+    import torch
+    base = S.scene_c5(n_starts=3, n_walks=512)
+    s = S.with_source(base, base["goal_c"])
+    rng = np.random.default_rng(5)
+    starts = []
+    while len(starts) < 4:
+        v = rng.normal(size=7)
+        p = base["goal_c"] + 0.12 * v / np.linalg.norm(v)
+        if S.is_clear(p, s, 0.05):
+            starts.append(p)
+    x0 = np.array(starts)
+    x = dev(x0, torch.float32)
+    dom = B.Domain(s)
+    plan = B.Plan(dom, x, 512, s["sigma"], s["eps"], s["s_ub"], s["seed"])
+    xo = np.ascontiguousarray(x0.astype(np.float32).astype(np.float64))
+    path = np.zeros(4)
+    stalls = np.zeros(4, dtype=np.int32)
+    status = np.zeros(4, dtype=np.int32)
+    for t in range(3):
+        plan.step(1)
+        u, g, pl, stl, sts, step = plan.read()
+        oracle.plan_step(s, xo, t, path, stalls, status)
+        xg = x.cpu().numpy().astype(np.float64)
+        assert np.array_equal(sts, status)
+        assert np.allclose(xg, xo, atol=2e-4), (t, np.abs(xg - xo).max())
+    plan.step(40)
+    sts = plan.read()[4]
+    assert np.all(sts == 1), sts
+    del plan
