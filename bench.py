@@ -151,6 +151,9 @@ class Batch:
         if mode == 2:
             envs = [S.with_bdata(e, 2, ak=S.plane_wave_k(e["d"], e["sigma"], seed=i))
                     for i, e in enumerate(envs)]
+        elif mode == 3:
+            # the paper's formulation: a unit impulse at the goal point, zero data
+            envs = [S.with_source(e, e["goal_c"]) for e in envs]
         self.doms = [B.Domain(e) for e in envs]
         Qs = [len(e["queries"]) for e in envs]
         self.off = np.concatenate([[0], np.cumsum(Qs)]).astype(np.int64)
@@ -236,11 +239,12 @@ def near_goal_starts(s, n, seed=5):
     return np.array(out)
 
 
-def planning(B, torch, n_steps, near_goal=False):
+def planning(B, torch, n_steps, near_goal=False, source=False):
     from paper_2406_01713_amd import scenes as S
-    s = S.scene_c5()
+    s0 = S.scene_c5()
+    starts = near_goal_starts(s0, len(s0["queries"])) if near_goal else s0["queries"]
+    s = S.with_source(s0, s0["goal_c"]) if source else s0
     dom = B.Domain(s)
-    starts = near_goal_starts(s, len(s["queries"])) if near_goal else s["queries"]
     x = torch.as_tensor(starts, dtype=torch.float32, device="cuda")
     plan = B.Plan(dom, x, s["n_walks"], s["sigma"], s["eps"], s["s_ub"], s["seed"])
     plan.step(1)
@@ -250,6 +254,7 @@ def planning(B, torch, n_steps, near_goal=False):
     u, g, pl, stalls, status, step = plan.read()
     dt = time.perf_counter() - t0
     res = {"starts": len(x), "start_set": "0.05-0.5 outside the goal sphere" if near_goal else "uniform free",
+           "goal": "unit impulse at the goal point, zero data" if source else "goal ball, g = 1",
            "steps": int(step[0]), "ms_per_step": 1000 * dt / max(1, n_steps - 1),
            "walks_per_gradient": s["n_walks"], "obstacles": "512 spheres + 512 boxes",
            "arrived": int((status == 1).sum()), "stopped_elsewhere": int((status == 2).sum()),
@@ -269,6 +274,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plan", action="store_true")
     ap.add_argument("--no-se", action="store_true")
+    ap.add_argument("--no-source", action="store_true", help="skip the point-source workload")
     ap.add_argument("--only-batched", action="store_true", help="time the batched step only (profiling)")
     ap.add_argument("--plan-steps", type=int, default=200)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -279,7 +285,7 @@ def main():
               "(multi-GPU sharding is described in DESIGN.md, not run). Use --gpus 1.", file=sys.stderr)
         sys.exit(2)
     if args.only_batched:
-        args.no_plain = args.no_cpu = args.no_plan = args.no_se = True
+        args.no_plain = args.no_cpu = args.no_plan = args.no_se = args.no_source = True
 
     t = time.perf_counter()
     envs = workload()
@@ -432,6 +438,47 @@ def main():
         out["se_note"] = ("SE from plane-wave boundary data on the same geometry and walks; "
                           f"with goal-indicator data {zero_hit}/{q_total} queries see no goal hit")
 
+    if not args.no_source:
+        # the same queries with the paper's point-source formulation (unit
+        # impulse at each env's goal point, zero boundary data, goal ball
+        # removed), fused forward + backward, one persistent launch
+        t = time.perf_counter()
+        ps = Batch(B, envs, torch, mode=3)
+        ps.run()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(2):
+            ps.run()
+        e1.record(st)
+        torch.cuda.synchronize()
+        ps_ms = e0.elapsed_time(e1) / 2
+        pst = ps.st.cpu().numpy()
+        pu = ps.u.cpu().numpy()
+        pg = ps.g.cpu().numpy().astype(np.float64)
+        ws = sum(float((pst[ps.off[e]:ps.off[e + 1], 9] * s["n_walks"]).sum()) for e, s in enumerate(envs))
+        need = have = 0.0
+        for e, s in enumerate(envs):
+            sl = slice(ps.off[e], ps.off[e + 1])
+            gn = np.linalg.norm(pg[sl, :s["d"]], axis=1)
+            se = np.linalg.norm(pst[sl, 1:1 + s["d"]], axis=1)
+            ok = gn > 0
+            need += float(np.sum(s["n_walks"] * (se[ok] / (0.01 * gn[ok])) ** 2))
+            have += float(ok.sum() * s["n_walks"])
+        q_total = int(ps.off[-1])
+        out["point_source_d7"] = {
+            "workload": "the same 84 envs and queries; unit impulse at each env's goal point, zero boundary "
+                        "data, goal ball removed; fused fwd+bwd, one persistent launch",
+            "ms_per_step": ps_ms, "walk_steps_per_s": ws / (ps_ms / 1e3), "walk_steps_per_step": ws,
+            "queries_with_signal": int((pu > 0).sum()), "queries": q_total,
+            "grad_queries_per_s_at_1pct_se": q_total / (ps_ms / 1e3 * need / max(have, 1.0)),
+            "se_note": "d = 7: the point-source estimator has infinite variance (contributions grow like "
+                       "r^(2-d) near the source), so sample SEs understate the error"}
+        log(f"point source: {ps_ms:.1f} ms/step, {ws / (ps_ms / 1e3):.3e} walk-steps/s, "
+            f"{int((pu > 0).sum())}/{q_total} queries with signal ({time.perf_counter() - t:.1f} s)")
+        del ps
+
     if not args.no_plan:
         t = time.perf_counter()
         out["planning_d7"] = planning(B, torch, args.plan_steps)
@@ -439,6 +486,14 @@ def main():
         log(f"planning: {out['planning_d7']['ms_per_step']:.1f} ms/step; near goal "
             f"{out['planning_d7_near_goal']['ms_per_step']:.1f} ms/step, "
             f"{out['planning_d7_near_goal']['arrived']} arrived ({time.perf_counter() - t:.1f} s)")
+        if not args.no_source:
+            t = time.perf_counter()
+            out["planning_d7_point_source"] = planning(B, torch, args.plan_steps, source=True)
+            out["planning_d7_point_source_near_goal"] = planning(B, torch, args.plan_steps, near_goal=True,
+                                                                 source=True)
+            log(f"planning to a point source: {out['planning_d7_point_source']['arrived']} / "
+                f"{out['planning_d7_point_source_near_goal']['arrived']} arrived "
+                f"({time.perf_counter() - t:.1f} s)")
 
     if cpu is not None:
         out["cpu_baseline"] = cpu
