@@ -328,10 +328,16 @@ __device__ __forceinline__ void run_unit(cenv<float> p, CBatch& be, int64_t loca
                 a[4] += (e.status == kDegenerate) ? 1.0 : 0.0;
                 a[5] += walk_dsigma<float, SRC>(e);
                 a[6] += (double)e.goal_w;
-                for (int i = 0; i < d; ++i) {
-                    const double gi = (double)walk_grad<float, kMaxDim, kMaxDim, SRC>(e, s.v0, p, xq, i);
-                    g[i * kWave] += gi;
-                    g[(kMaxDim + i) * kWave] += gi * gi;
+                // static indices (unrolled, guarded by d) keep the walker in
+                // registers; a runtime loop bound would index it dynamically
+                // and move it to scratch memory
+#pragma unroll
+                for (int i = 0; i < kMaxDim; ++i) {
+                    if (i < d) {
+                        const double gi = (double)walk_grad<float, kMaxDim, kMaxDim, SRC>(e, s.v0, p, xq, i);
+                        g[i * kWave] += gi;
+                        g[(kMaxDim + i) * kWave] += gi * gi;
+                    }
                 }
             }
         }
