@@ -75,6 +75,7 @@ def lib():
         L.or_hyp0f1.restype = C.c_double
         L.or_bessel_k.argtypes = [C.c_double, C.c_double]
         L.or_bessel_k.restype = C.c_double
+        L.or_varadhan.argtypes = [C.c_int, C.c_double, C.c_double, dp, dp, dp]
         L.or_yukawa_free.argtypes = [C.c_int, C.c_double, C.c_double]
         L.or_yukawa_free.restype = C.c_double
         for f in ("or_ball_green", "or_ball_green_grad", "or_ball_green_dsigma"):
@@ -202,6 +203,16 @@ def boundary_value(scene_or_dom, x, cls, idx):
 
 def hyp0f1(b, y):
     return lib().or_hyp0f1(float(b), float(y))
+
+
+def varadhan(sigma, u, grad_u=None):
+    """(w, grad_w) = (-sqrt(t) ln u, -sqrt(t) grad_u / u), t = 1 / sigma."""
+    g = np.ascontiguousarray(np.zeros(1) if grad_u is None else np.asarray(grad_u, dtype=np.float64))
+    d = len(g) if grad_u is not None else 0
+    w = C.c_double()
+    gw = np.zeros(max(d, 1))
+    lib().or_varadhan(d, float(sigma), float(u), _dp(g), C.byref(w), _dp(gw) if grad_u is not None else None)
+    return (w.value, gw[:d].copy()) if grad_u is not None else w.value
 
 
 def bessel_k(nu, z):

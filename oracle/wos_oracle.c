@@ -498,6 +498,23 @@ void or_walk(const or_domain* D, const double* xq, double sigma, double eps, uin
 }
 
 /* ------------------------------------------------------------------------ */
+/* Varadhan read-out (Sec. III, eq. transformation_varadhan):                 */
+/* w = -sqrt(t) ln u with t = 1 / sigma, grad w = -sqrt(t) grad u / u.        */
+/* u <= 0 (no signal) gives w = +inf and grad w = 0.                          */
+/* ------------------------------------------------------------------------ */
+void or_varadhan(int d, double sigma, double u, const double* grad_u, double* w, double* grad_w)
+{
+    double st = 1.0 / sqrt(sigma);
+    if (!(u > 0.0)) {
+        *w = INFINITY;
+        if (grad_w) for (int i = 0; i < d; ++i) grad_w[i] = 0.0;
+        return;
+    }
+    *w = -st * log(u);
+    if (grad_w) for (int i = 0; i < d; ++i) grad_w[i] = -st * grad_u[i] / u;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Per-query mean of the one-point estimates (Sec. IV-A) and standard errors. */
 /* stats row (d + 4): se_u, se_grad[d], mean_steps, n_trunc, n_degen.         */
 /* Optional per-query backward sums: dq row (2): mean(u_hat S), mean(goal_w). */
