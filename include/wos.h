@@ -294,6 +294,22 @@ int wos_autotune(int d, int64_t n_obstacles, int64_t n_queries, int64_t n_walks,
 int wos_set_autotune_cache(const char* cache_path);
 
 /*
+ * wos_varadhan -- the Varadhan read-out of an estimate (Sec. III, eq.
+ * transformation_varadhan): w = -sqrt(t) ln u with t = 1 / sigma, a distance
+ * to the goal set that tends to the geodesic one as t -> 0, and
+ * grad w = -sqrt(t) grad u / u (parallel to grad u, Sec. III).
+ *   u          device, n (float or double per opt->flags)
+ *   grad_u     device, n x stride (first d columns used), or NULL
+ *   sigma      the screening coefficient the estimate was made with, > 0
+ *   out_w      device, n; +inf where u <= 0 (no walk reached the goal)
+ *   out_grad_w device, n x stride, or NULL (with grad_u); 0 where u <= 0
+ * Asynchronous on stream.  Errors: WOS_EINVAL (sigma <= 0, NULL u / out_w,
+ * grad_u without out_grad_w, stride < d), WOS_EDIM, WOS_EHIP.
+ */
+int wos_varadhan(const void* u, const void* grad_u, int64_t n, int d, int stride, double sigma,
+                 void* out_w, void* out_grad_w, const wos_options* opt, void* stream);
+
+/*
  * wos_debug_walks -- per-walk records of walks w0 .. w0+n-1 of one query, for
  * diagnostics and walk-level parity checks.  query is a host double array of
  * d values (cast to the compute type); q_index is the query's RNG index.

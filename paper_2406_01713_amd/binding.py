@@ -28,7 +28,7 @@ MAX_DIM = 8
 EXPORTED = ["wos_create_domain", "wos_destroy_domain", "wos_domain_dim", "wos_estimate",
             "wos_backward", "wos_estimate_batch", "wos_plan_create", "wos_plan_step",
             "wos_plan_buffers", "wos_plan_read", "wos_plan_destroy", "wos_autotune", "wos_set_autotune_cache",
-            "wos_debug_walks", "wos_debug_clusters", "wos_microbench", "wos_last_error"]
+            "wos_debug_walks", "wos_debug_clusters", "wos_varadhan", "wos_microbench", "wos_last_error"]
 
 
 class WosError(RuntimeError):
@@ -101,6 +101,7 @@ def _load():
     L.wos_debug_clusters.argtypes = [C.c_int, C.POINTER(Spheres), C.POINTER(Boxes), C.c_int,
                                      C.POINTER(i64), C.POINTER(i64), dp, C.POINTER(i64), dp]
     L.wos_microbench.argtypes = [C.c_int, dp, dp]
+    L.wos_varadhan.argtypes = [vp, vp, i64, C.c_int, C.c_int, C.c_double, vp, vp, C.POINTER(Options), vp]
     L.wos_last_error.restype = C.c_char_p
     return L
 
@@ -272,6 +273,22 @@ def wos_debug_clusters(d, sph_c=None, sph_r=None, box_c=None, box_h=None, fp64=F
     p64 = lambda a: a.ctypes.data_as(C.POINTER(C.c_int64))
     check(lib.wos_debug_clusters(*args, n_cl, p64(o_s), _dp(b_s), p64(o_b), _dp(b_b)))
     return {"sph": (o_s, b_s), "box": (o_b, b_b)}
+
+
+def wos_varadhan(u, sigma, grad_u=None, out_w=None, out_grad_w=None, opt=None, stream=None):
+    """Varadhan read-out w = -sqrt(1/sigma) ln u (and grad w) on device tensors."""
+    import torch
+    if opt is None:
+        opt = options(fp64=(u.dtype == torch.float64))
+    out_w = torch.empty_like(u) if out_w is None else out_w
+    d = stride = 0
+    if grad_u is not None:
+        stride = grad_u.shape[1]
+        d = stride if stride <= MAX_DIM else MAX_DIM
+        out_grad_w = torch.empty_like(grad_u) if out_grad_w is None else out_grad_w
+    check(lib.wos_varadhan(_ptr(u), _ptr(grad_u), u.shape[0], d, stride, float(sigma), _ptr(out_w),
+                           _ptr(out_grad_w), C.byref(opt) if opt is not None else None, _stream(stream)))
+    return (out_w, out_grad_w) if grad_u is not None else out_w
 
 
 def wos_microbench(which):

@@ -859,6 +859,30 @@ void wos_destroy_domain(wos_domain* D)
 
 int wos_domain_dim(const wos_domain* D) { return D ? D->d : fail(WOS_EINVAL, "domain is NULL"); }
 
+int wos_varadhan(const void* u, const void* grad_u, int64_t n, int d, int stride, double sigma, void* out_w,
+                 void* out_grad_w, const wos_options* opt, void* stream)
+{
+    wos_options o;
+    int rc = read_opts(opt, o);
+    if (rc) return rc;
+    if (n < 0) return fail(WOS_EINVAL, "n < 0");
+    if (!(sigma > 0.0) || !std::isfinite(sigma)) return fail(WOS_EINVAL, "sigma must be finite and > 0 (t = 1/sigma)");
+    if (n > 0 && (!u || !out_w)) return fail(WOS_EINVAL, "u and out_w are required");
+    if ((grad_u == nullptr) != (out_grad_w == nullptr)) return fail(WOS_EINVAL, "grad_u and out_grad_w go together");
+    if (grad_u && (d < WOS_MIN_DIM || d > WOS_MAX_DIM)) return fail(WOS_EDIM, "d = %d outside [%d, %d]", d, WOS_MIN_DIM, WOS_MAX_DIM);
+    if (grad_u && stride < d) return fail(WOS_EINVAL, "stride < d");
+    hipStream_t st = (hipStream_t)stream;
+    if (o.flags & WOS_FP64)
+        WOS_HIP(launch_varadhan<double>((const double*)u, (const double*)grad_u, n, d, stride, sigma, (double*)out_w,
+                                        (double*)out_grad_w, st),
+                "varadhan");
+    else
+        WOS_HIP(launch_varadhan<float>((const float*)u, (const float*)grad_u, n, d, stride, sigma, (float*)out_w,
+                                       (float*)out_grad_w, st),
+                "varadhan");
+    return WOS_OK;
+}
+
 int wos_debug_clusters(int d, const wos_spheres* spheres, const wos_boxes* boxes, int fp64, int64_t* out_n_cl,
                        int64_t* order_sph, double* bnd_sph, int64_t* order_box, double* bnd_box)
 {

@@ -17,6 +17,8 @@
 // the paper (screened WoS, first-sphere gradient), the step rule Sec. VII.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
+
 #include "wos_device.hpp"
 #include "wos_launch.hpp"
 
@@ -521,6 +523,27 @@ plan_update(const EnvP<float>* penv, float* __restrict__ x, int64_t n, const flo
     if (blockIdx.x == 0 && threadIdx.x == 0) *step += 1;
 }
 
+// ------------------------------------------------------------------------
+// Varadhan read-out (Sec. III, eq. transformation_varadhan): w = -sqrt(t) ln u,
+// t = 1 / sigma, grad w = -sqrt(t) grad u / u; u <= 0 (no signal) gives
+// w = +inf and grad w = 0.  One thread per query.
+// ------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+varadhan_kernel(const T* __restrict__ u, const T* __restrict__ grad, int64_t n, int d, int stride,
+                T sqrt_t, T* __restrict__ w, T* __restrict__ grad_w)
+{
+    const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (q >= n) return;
+    const T uq = u[q];
+    const bool ok = uq > T(0);
+    w[q] = ok ? -sqrt_t * ::log(uq) : Math<T>::inf();
+    if (grad_w) {
+        const T f = ok ? -sqrt_t / uq : T(0);
+        for (int i = 0; i < d; ++i) grad_w[q * stride + i] = f * grad[q * stride + i];
+    }
+}
+
 __global__ void fill_u32(unsigned* p, int64_t n, unsigned v)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -717,6 +740,21 @@ hipError_t launch_plan_update(int d, const EnvP<float>* p, float* x, int64_t n, 
 #undef WOS_PLAN_CASE
     return hipGetLastError();
 }
+
+template <typename T>
+hipError_t launch_varadhan(const T* u, const T* grad, int64_t n, int d, int stride, double sigma, T* w,
+                           T* grad_w, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    const T sqrt_t = (T)(1.0 / std::sqrt(sigma));
+    hipLaunchKernelGGL((varadhan_kernel<T>), dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, st, u, grad, n, d,
+                       stride, sqrt_t, w, grad_w);
+    return hipGetLastError();
+}
+template hipError_t launch_varadhan<float>(const float*, const float*, int64_t, int, int, double, float*, float*,
+                                           hipStream_t);
+template hipError_t launch_varadhan<double>(const double*, const double*, int64_t, int, int, double, double*,
+                                            double*, hipStream_t);
 
 hipError_t launch_fill_u32(unsigned* p, int64_t n, unsigned v, hipStream_t st)
 {

@@ -52,6 +52,12 @@ hipError_t launch_plan_update(int d, const EnvP<float>* p, float* x, int64_t n, 
                               int grad_stride, float s_ub, double* path_len, int32_t* stalls,
                               int32_t* status, uint64_t* step, hipStream_t st);
 
+// Varadhan read-out w = -sqrt(1/sigma) ln u (and its gradient when grad and
+// grad_w are given, rows of `stride` elements, first d used).
+template <typename T>
+hipError_t launch_varadhan(const T* u, const T* grad, int64_t n, int d, int stride, double sigma, T* w,
+                           T* grad_w, hipStream_t st);
+
 // Fill kernels (used instead of hipMemsetAsync so the calls are capturable).
 hipError_t launch_fill_u32(unsigned* p, int64_t n, unsigned v, hipStream_t st);
 hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t st);

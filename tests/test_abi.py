@@ -127,3 +127,14 @@ def test_create_domain_rejects_bad_source(B):
         rc = B.lib.wos_create_domain(d, None, None, None, C.byref(o), C.byref(bd), C.byref(src), C.byref(h))
         assert rc == B.WOS_EINVAL
         assert b"source" in B.lib.wos_last_error()
+
+
+def test_varadhan_rejects_bad_arguments(B):
+    vp = C.c_void_p(1)
+    assert B.lib.wos_varadhan(vp, None, 4, 0, 0, 0.0, vp, None, None, None) == B.WOS_EINVAL
+    assert B.lib.wos_varadhan(vp, None, 4, 0, 0, -1.0, vp, None, None, None) == B.WOS_EINVAL
+    assert B.lib.wos_varadhan(None, None, 4, 0, 0, 1.0, vp, None, None, None) == B.WOS_EINVAL
+    assert B.lib.wos_varadhan(vp, vp, 4, 3, 3, 1.0, vp, None, None, None) == B.WOS_EINVAL
+    assert B.lib.wos_varadhan(vp, vp, 4, 9, 9, 1.0, vp, vp, None, None) == B.WOS_EDIM
+    assert B.lib.wos_varadhan(vp, vp, 4, 3, 2, 1.0, vp, vp, None, None) == B.WOS_EINVAL
+    assert B.lib.wos_varadhan(None, None, 0, 0, 0, 1.0, None, None, None, None) == B.WOS_OK
