@@ -67,6 +67,8 @@ extern "C" {
 #define WOS_FP64 1u
 #define WOS_FULL_SCAN 2u /* scan every obstacle each step (no cluster culling);
                             same walks and results, more work: for testing */
+#define WOS_SCALAR_CULL 4u /* FP32: cluster tests on the vector ALUs instead of the
+                              matrix cores; same walks and results */
 
 /* boundary-data modes */
 #define WOS_BDATA_CLASS 0  /* g_goal / g_obstacle / g_outer per component */
@@ -128,7 +130,7 @@ typedef struct {
 } wos_source;
 
 typedef struct {
-    uint32_t flags;     /* WOS_FP32 (default) or WOS_FP64, optionally | WOS_FULL_SCAN */
+    uint32_t flags;     /* WOS_FP32 (default) or WOS_FP64, optionally | WOS_FULL_SCAN, WOS_SCALAR_CULL */
     uint32_t env_id;    /* counter word 3 of the RNG (default 0) */
     uint32_t max_steps; /* distance evaluations per walk before truncation; 0 -> 65536 */
     uint32_t reserved;  /* must be 0 */

@@ -86,6 +86,7 @@ struct wos_domain {
     float* cl_f = nullptr;
     double* cl_d = nullptr;
     size_t off_sph_bnd = 0, off_box_cl = 0, off_box_bnd = 0;
+    size_t off_sph_mf = 0, off_box_mf = 0;  // matrix-core features (FP32 buffer only)
 };
 
 namespace {
@@ -148,6 +149,9 @@ int make_env(const wos_domain* D, double sigma, double eps, uint64_t seed, uint3
     p.sph_bnd = cl ? cl + D->off_sph_bnd : nullptr;
     p.box_cl = cl ? cl + D->off_box_cl : nullptr;
     p.box_bnd = cl ? cl + D->off_box_bnd : nullptr;
+    p.sph_mf = D->cl_f ? D->cl_f + D->off_sph_mf : nullptr;
+    p.box_mf = D->cl_f ? D->cl_f + D->off_box_mf : nullptr;
+    p.use_mfma = (sizeof(T) == 4 && !(o.flags & WOS_SCALAR_CULL)) ? 1 : 0;
     p.d = D->d;
     p.has_goal = D->has_goal ? 1 : 0;
     p.outer_kind = D->outer_kind;
@@ -402,6 +406,38 @@ int64_t cluster_order(int d, int64_t n, const double* centers, std::vector<int64
     return (n + kCluster - 1) / kCluster;
 }
 
+// Matrix-core cluster features (see kMfmaTile) from the FP32 bound rows:
+// out holds ceil(n_cl / 16) tiles of 64 x 4 floats.
+void build_mfma_features(int d, int64_t n_cl, const float* bnd, float* out)
+{
+    const int SB = sph_stride(d);
+    const double m = 0x1p-12;
+    const int64_t n_tiles = (n_cl + kMfmaTile - 1) / kMfmaTile;
+    for (int64_t t = 0; t < n_tiles; ++t)
+        for (int lane = 0; lane < 64; ++lane) {
+            const int j = lane % kMfmaTile, k = lane / kMfmaTile;
+            const int64_t g = t * kMfmaTile + j;
+            double f[kMfmaFeat];
+            if (g < n_cl) {
+                const float* b = bnd + g * SB;
+                double cc = 0.0;
+                for (int i = 0; i < d; ++i) cc += (double)b[i] * (double)b[i];
+                const double rho = (double)b[d];
+                for (int i = 0; i < 8; ++i) f[i] = i < d ? -2.0 * (double)b[i] : 0.0;
+                f[8] = 1.0;
+                f[9] = cc * (1.0 - m) - rho * rho * (1.0 + m);
+                f[10] = -1.0;
+                f[11] = -2.0 * rho;
+            } else {
+                for (int i = 0; i < kMfmaFeat; ++i) f[i] = 0.0;
+                f[9] = 1e30;  // always skipped
+            }
+            float* o = out + (t * 64 + lane) * 4;
+            for (int s = 0; s < 3; ++s) o[s] = (float)f[4 * s + k];
+            o[3] = 0.0f;
+        }
+}
+
 int check_device(const wos_domain* D)
 {
     int dev = -1;
@@ -414,7 +450,7 @@ int read_opts(const wos_options* opt, wos_options& o)
 {
     o = wos_options{WOS_FP32, 0u, 0u, 0u};
     if (opt) o = *opt;
-    if (o.flags & ~(WOS_FP64 | WOS_FULL_SCAN)) return fail(WOS_EINVAL, "unknown flags 0x%x", o.flags);
+    if (o.flags & ~(WOS_FP64 | WOS_FULL_SCAN | WOS_SCALAR_CULL)) return fail(WOS_EINVAL, "unknown flags 0x%x", o.flags);
     if (o.reserved != 0) return fail(WOS_EINVAL, "wos_options.reserved must be 0");
     return WOS_OK;
 }
@@ -819,8 +855,14 @@ int wos_create_domain(int d, const wos_spheres* spheres, const wos_boxes* boxes,
     D->off_box_cl = D->off_sph_bnd + nbs * sb;
     D->off_box_bnd = D->off_box_cl + (size_t)D->n_cl_box * kCluster * bs;
     const size_t cl_elems = D->off_box_bnd + nbb * sb;
+    // matrix-core features live in the FP32 buffer only, after the tables
+    const size_t mf_s = (size_t)((D->n_cl_sph + kMfmaTile - 1) / kMfmaTile) * 64 * 4;
+    const size_t mf_b = (size_t)((D->n_cl_box + kMfmaTile - 1) / kMfmaTile) * 64 * 4;
+    D->off_sph_mf = (cl_elems + 3) / 4 * 4;  // 16-byte aligned float4 rows
+    D->off_box_mf = D->off_sph_mf + mf_s;
+    const size_t cf_elems = D->off_box_mf + mf_b;
     if (e == hipSuccess && cl_elems > 0) {
-        std::vector<float> cf(cl_elems, 0.f);
+        std::vector<float> cf(cf_elems, 0.f);
         std::vector<double> cd(cl_elems, 0.0);
         if (D->n_cl_sph) {
             build_clusters<float>(d, ns, false, idx_s, sf.data(), ss, cf.data(), cf.data() + D->off_sph_bnd);
@@ -832,9 +874,13 @@ int wos_create_domain(int d, const wos_spheres* spheres, const wos_boxes* boxes,
             build_clusters<double>(d, nb, true, idx_b, bd.data(), bs, cd.data() + D->off_box_cl,
                                    cd.data() + D->off_box_bnd);
         }
-        e = hipMalloc(&D->cl_f, cl_elems * sizeof(float));
+        if (D->n_cl_sph)
+            build_mfma_features(d, D->n_cl_sph, cf.data() + D->off_sph_bnd, cf.data() + D->off_sph_mf);
+        if (D->n_cl_box)
+            build_mfma_features(d, D->n_cl_box, cf.data() + D->off_box_bnd, cf.data() + D->off_box_mf);
+        e = hipMalloc(&D->cl_f, cf_elems * sizeof(float));
         if (e == hipSuccess) e = hipMalloc(&D->cl_d, cl_elems * sizeof(double));
-        if (e == hipSuccess) e = hipMemcpy(D->cl_f, cf.data(), cl_elems * sizeof(float), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(D->cl_f, cf.data(), cf_elems * sizeof(float), hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMemcpy(D->cl_d, cd.data(), cl_elems * sizeof(double), hipMemcpyHostToDevice);
     }
     if (e != hipSuccess) {

@@ -322,6 +322,90 @@ __device__ __forceinline__ T cluster_min(cptr<T> rows, cptr<T> bnd, int n_cl, co
     return best;
 }
 
+// ------------------------------------------------------------------------
+// Cluster test on the matrix cores (FP32).  The walker and cluster feature
+// vectors (see kMfmaTile) make the test a 12-term dot product per (walker,
+// cluster) pair: three v_mfma_f32_16x16x4f32 per tile of 16 walkers x 16
+// clusters.  Requires every lane of the wave to be active (the callers step
+// all lanes); lanes with live false get a huge feature 8 and never demand a
+// cluster.
+// ------------------------------------------------------------------------
+typedef float mf4 __attribute__((ext_vector_type(4)));
+
+// Walker features transposed into the A operands: A[s][t] is the operand of
+// K-step s (features 4s..4s+3) for the row tile of walkers 16t..16t+15; lane
+// 16h + i holds feature 4s + h of walker 16t + i.  Two permlane16 swaps then
+// two permlane32 swaps transpose (feature, 16-lane row) blocks.
+template <int D>
+__device__ __forceinline__ void mfma_walker_operands(const float (&x)[D], float thr, bool live, float (&A)[3][4])
+{
+    float f[kMfmaFeat];
+    float xx = 0.0f;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        f[i] = i < D ? x[i < D ? i : 0] : 0.0f;
+        if (i < D) xx = __builtin_fmaf(f[i], f[i], xx);
+    }
+    const float m = 0x1p-12f;
+    f[8] = live ? __builtin_fmaf(xx, 1.0f - m, -m * thr * thr) : 1e30f;
+    f[9] = 1.0f;
+    f[10] = thr * thr;
+    f[11] = thr;
+#pragma unroll
+    for (int st = 0; st < 3; ++st) {
+        unsigned r0 = __float_as_uint(f[4 * st]), r1 = __float_as_uint(f[4 * st + 1]);
+        unsigned r2 = __float_as_uint(f[4 * st + 2]), r3 = __float_as_uint(f[4 * st + 3]);
+        const auto p01 = __builtin_amdgcn_permlane16_swap(r0, r1, false, false);
+        const auto p23 = __builtin_amdgcn_permlane16_swap(r2, r3, false, false);
+        const auto q02 = __builtin_amdgcn_permlane32_swap(p01[0], p23[0], false, false);
+        const auto q13 = __builtin_amdgcn_permlane32_swap(p01[1], p23[1], false, false);
+        A[st][0] = __uint_as_float(q02[0]);
+        A[st][1] = __uint_as_float(q13[0]);
+        A[st][2] = __uint_as_float(q02[1]);
+        A[st][3] = __uint_as_float(q13[1]);
+    }
+}
+
+// Min over the members of the clusters some live walker of the wave may need,
+// deciding 16 clusters at a time on the matrix cores: D[i][j] (walker i,
+// cluster j) lands in lane j + 16 (i / 4), register i % 4, so the clusters
+// any walker keeps are the low 16 bits of the OR of the four register votes
+// folded over the lane groups.  NaN never skips.  thr as for cluster_min.
+template <int D, bool BOX>
+__device__ __forceinline__ float cluster_min_mfma(cptr<float> rows, const float* __restrict__ mf, int n_cl,
+                                                  const float (&x)[D], float thr, bool live, uint32_t& n_eval)
+{
+    constexpr int S = BOX ? box_stride(D) : sph_stride(D);
+    float A[3][4];
+    mfma_walker_operands<D>(x, thr, live, A);
+    const mf4* tab = reinterpret_cast<const mf4*>(mf) + (threadIdx.x & (kWave - 1));
+    const int n_tiles = (n_cl + kMfmaTile - 1) / kMfmaTile;
+    float best = Math<float>::inf();
+    for (int t = 0; t < n_tiles; ++t) {
+        const mf4 b = tab[t * kWave];
+        uint64_t keep = 0;
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt) {
+            mf4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(A[0][rt], b[0], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(A[1][rt], b[1], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(A[2][rt], b[2], acc, 0, 0, 0);
+            keep |= __ballot(!(acc[0] > 0.0f)) | __ballot(!(acc[1] > 0.0f)) | __ballot(!(acc[2] > 0.0f)) |
+                    __ballot(!(acc[3] > 0.0f));
+        }
+        keep |= keep >> 32;
+        keep |= keep >> 16;
+        uint32_t mask = (uint32_t)keep & 0xFFFFu;
+        while (mask) {  // wave-uniform
+            const int j = __builtin_ctz(mask);
+            mask &= mask - 1u;
+            best = cluster_members_min<float, D, BOX>(x, rows + (t * kMfmaTile + j) * (kCluster * S), best);
+            n_eval += kCluster;
+        }
+    }
+    return best;
+}
+
 // Obstacle distances evaluated, summed over the live lanes of a wave: the
 // scans are wave-uniform, so every lane evaluates the same rows, and the
 // tally is one wave-level count for the work statistics.  Callers run the
@@ -355,8 +439,17 @@ __device__ __forceinline__ T distance(cenv<T> p, const T (&x)[D], int& cls, Work
     uint32_t nb, ns;
     if (p->n_cl_box) {
         nb = 0;
-        db = cluster_min<T, D, true>(to_const(p->box_cl), to_const(fresh(p)->box_bnd), fresh(p)->n_cl_box, x,
-                                     Math<T>::min(dg, dout), live, nb);
+        bool done = false;
+        if constexpr (sizeof(T) == 4) {
+            if (p->use_mfma) {
+                db = cluster_min_mfma<D, true>(to_const(p->box_cl), fresh(p)->box_mf, fresh(p)->n_cl_box, x,
+                                               Math<T>::min(dg, dout), live, nb);
+                done = true;
+            }
+        }
+        if (!done)
+            db = cluster_min<T, D, true>(to_const(fresh(p)->box_cl), to_const(fresh(p)->box_bnd), fresh(p)->n_cl_box, x,
+                                         Math<T>::min(dg, dout), live, nb);
     } else {
         db = boxes_min<T, D>(to_const(p->box), fresh(p)->n_box, x);
         nb = (uint32_t)fresh(p)->n_box;
@@ -365,8 +458,17 @@ __device__ __forceinline__ T distance(cenv<T> p, const T (&x)[D], int& cls, Work
     T ds;
     if (p->n_cl_sph) {
         ns = 0;
-        ds = cluster_min<T, D, false>(to_const(p->sph_cl), to_const(fresh(p)->sph_bnd), fresh(p)->n_cl_sph, x,
-                                      Math<T>::min(Math<T>::min(dg, dout), db), live, ns);
+        bool done = false;
+        if constexpr (sizeof(T) == 4) {
+            if (p->use_mfma) {
+                ds = cluster_min_mfma<D, false>(to_const(p->sph_cl), fresh(p)->sph_mf, fresh(p)->n_cl_sph, x,
+                                                Math<T>::min(Math<T>::min(dg, dout), db), live, ns);
+                done = true;
+            }
+        }
+        if (!done)
+            ds = cluster_min<T, D, false>(to_const(fresh(p)->sph_cl), to_const(fresh(p)->sph_bnd), fresh(p)->n_cl_sph,
+                                          x, Math<T>::min(Math<T>::min(dg, dout), db), live, ns);
     } else {
         ds = spheres_min<T, D>(to_const(p->sph), fresh(p)->n_sph, x);
         ns = (uint32_t)fresh(p)->n_sph;

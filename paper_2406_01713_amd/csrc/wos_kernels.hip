@@ -484,13 +484,17 @@ plan_update(const EnvP<float>* penv, float* __restrict__ x, int64_t n, const flo
 {
     const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const cenv<float> p = (cenv<float>)penv;
-    if (s < n) {
-        float xs[D];
+    // every lane evaluates the distance (the matrix-core cluster test needs
+    // the whole wave); lanes past n use start 0 (or the origin) and write nothing
+    const bool valid = s < n;
+    const int64_t si = valid ? s : 0;
+    float xs[D];
 #pragma unroll
-        for (int i = 0; i < D; ++i) xs[i] = x[s * D + i];
-        int cls;
-        WorkCount wc{0, 0};
-        const float R = distance<float, D>(p, xs, cls, wc, true);
+    for (int i = 0; i < D; ++i) xs[i] = (n > 0) ? x[si * D + i] : 0.0f;
+    int cls;
+    WorkCount wc{0, 0};
+    const float R = distance<float, D>(p, xs, cls, wc, valid);
+    if (valid) {
         float dz2 = 0.0f;
         if (p->has_src) {
 #pragma unroll

@@ -31,6 +31,21 @@ __host__ __device__ constexpr int box_stride(int d) { return ((2 * d + 3) / 4) *
 constexpr int kCluster = 8;
 constexpr int kClusterMin = 64;
 
+// Matrix-core form of the cluster test (FP32 kernels).  With walker features
+//   a = [x (8 slots, 0 past d), |x|^2 (1 - m) - m thr^2, 1, thr^2, thr]
+// and cluster features
+//   b = [-2 C (8 slots), 1, |C|^2 (1 - m) - rho'^2 (1 + m), -1, -2 rho'],
+// m = 2^-12, the dot product is |x - C|^2 - (thr + rho')^2 - m (|x|^2 + thr^2
+// + |C|^2 + rho'^2); a cluster is skipped when it is positive for every
+// walker of the wave.  The margin m (4096 units of rounding) exceeds the
+// rounding of the products and of the members' own distances.  Cluster
+// features are stored per tile of 16 clusters as 64 lanes x 4 floats: lane
+// j + 16 k holds features k, 4 + k, 8 + k of cluster j of the tile (the B
+// operand of three 16x16x4 products), the 4th float unused.  Padding
+// clusters of the last tile have feature 9 = 1e30 (always skipped).
+constexpr int kMfmaTile = 16;
+constexpr int kMfmaFeat = 12;
+
 // Per-environment parameters of one walk launch.  Read by every lane with
 // wave-uniform addresses, so the compiler keeps them in scalar registers.
 template <typename T>
@@ -41,8 +56,11 @@ struct EnvP {
     const T* box_cl;       // n_cl_box x kCluster box rows, cluster order
     const T* sph_bnd;      // n_cl_sph + 1 bounding spheres, sph_stride(d) each (last: unused)
     const T* box_bnd;      // n_cl_box + 1 bounding spheres, sph_stride(d) each (last: unused)
+    const float* sph_mf;   // matrix-core cluster features, ceil(n_cl_sph / 16) x 64 x 4 (FP32 only)
+    const float* box_mf;
     int32_t n_sph, n_box;
     int32_t n_cl_sph, n_cl_box;  // 0: scan the caller-order table instead
+    int32_t use_mfma, pad_mf;    // 1: cluster tests on the matrix cores (FP32 kernels)
     int32_t d, has_goal;
     int32_t outer_kind, mode;  // outer: 0 box, 1 ball; mode: 0 class, 1 affine, 2 plane
     int32_t nt_C, nt_C1;       // Horner terms of 0F1(;d/2;y) and 0F1(;d/2+1;y)
