@@ -39,6 +39,7 @@ class OrDomain(C.Structure):
         ("outer_c", C.c_double * MAXD), ("outer_r", C.c_double),
         ("mode", C.c_int), ("g_goal", C.c_double), ("g_obs", C.c_double),
         ("g_outer", C.c_double), ("ak", C.c_double * MAXD), ("b", C.c_double),
+        ("geom_d", C.c_int),
     ]
 
 
@@ -130,6 +131,7 @@ class Domain:
             for i in range(d):
                 D.goal_c[i] = float(scene["goal_c"][i])
             D.goal_r = float(scene["goal_r"])
+        D.geom_d = int(scene.get("geom_d") or 0)  # 0: the full space
         o = scene["outer"]
         if o["kind"] == "box":
             D.outer_kind = 0

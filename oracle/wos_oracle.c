@@ -39,6 +39,11 @@
  *       grad_hat u(x_0) = (d / R_0) C1(R_0) u_hat(x_1) v_0
  *                         + c_imp amp grad_x G_B(x_0, z) 1{|z - x_0| < R_0},
  *   with u_hat(x_1) the same sum over the walk from x_1 (weights W1_k).
+ *   Extruded geometry (Sec. VI, the evaluation environment): the obstacles
+ *   and the outer boundary may depend on the first geom_d coordinates only,
+ *   the others being unbounded; their distances and closest points are then
+ *   taken in those coordinates, the goal ball and the source stay
+ *   d-dimensional.
  *
  * Random numbers: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11), key =
  * 64-bit seed, counter = (2k + j, walk, query, env) for step k and block j;
@@ -79,6 +84,8 @@ typedef struct {
     double g_goal, g_obs, g_outer;
     double ak[OR_MAXD];
     double b;
+    int geom_d; /* 0 or d: full space; else obstacles and the outer boundary
+                   depend on x[0..geom_d) only (extruded, Sec. VI) */
 } or_domain;
 
 typedef struct {
@@ -180,11 +187,15 @@ static double dist_box_signed(int d, const double* x, const double* c, const dou
     return sqrt(outside2) + (inside < 0.0 ? inside : 0.0);
 }
 
+/* coordinates the obstacles and the outer boundary depend on */
+static int geom_dim(const or_domain* D) { return D->geom_d > 0 ? D->geom_d : D->d; }
+
 static double dist_outer(const or_domain* D, const double* x)
 {
+    int g = geom_dim(D);
     if (D->outer_kind == 0) {
         double m = INFINITY;
-        for (int i = 0; i < D->d; ++i) {
+        for (int i = 0; i < g; ++i) {
             double a = x[i] - D->lo[i], b = D->hi[i] - x[i];
             if (a < m) m = a;
             if (b < m) m = b;
@@ -192,13 +203,13 @@ static double dist_outer(const or_domain* D, const double* x)
         return m;
     }
     double s = 0.0;
-    for (int i = 0; i < D->d; ++i) s += (x[i] - D->outer_c[i]) * (x[i] - D->outer_c[i]);
+    for (int i = 0; i < g; ++i) s += (x[i] - D->outer_c[i]) * (x[i] - D->outer_c[i]);
     return D->outer_r - sqrt(s);
 }
 
 double or_distance(const or_domain* D, const double* x, int* cls, int* idx)
 {
-    int d = D->d;
+    int d = D->d, g = geom_dim(D);
     double best = INFINITY;
     int bc = OR_OUTER, bi = 0;
     if (D->has_goal) {
@@ -206,11 +217,11 @@ double or_distance(const or_domain* D, const double* x, int* cls, int* idx)
         bc = OR_GOAL;
     }
     for (int j = 0; j < D->n_sph; ++j) {
-        double dj = dist_ball_outside(d, x, D->sph_c + (size_t)j * d, D->sph_r[j]);
+        double dj = dist_ball_outside(g, x, D->sph_c + (size_t)j * d, D->sph_r[j]);
         if (dj < best) { best = dj; bc = OR_SPHERE; bi = j; }
     }
     for (int j = 0; j < D->n_box; ++j) {
-        double dj = dist_box_signed(d, x, D->box_c + (size_t)j * d, D->box_h + (size_t)j * d);
+        double dj = dist_box_signed(g, x, D->box_c + (size_t)j * d, D->box_h + (size_t)j * d);
         if (dj < best) { best = dj; bc = OR_BOX; bi = j; }
     }
     double dout = dist_outer(D, x);
@@ -225,6 +236,8 @@ double or_distance(const or_domain* D, const double* x, int* cls, int* idx)
 void or_closest_point(const or_domain* D, const double* x, int cls, int idx, double* xbar)
 {
     int d = D->d;
+    /* an extruded component moves the first g coordinates, keeps the rest */
+    int g = cls == OR_GOAL ? d : geom_dim(D);
     memcpy(xbar, x, sizeof(double) * (size_t)d);
     if (cls == OR_GOAL || cls == OR_SPHERE || (cls == OR_OUTER && D->outer_kind == 1)) {
         const double* c;
@@ -233,24 +246,24 @@ void or_closest_point(const or_domain* D, const double* x, int cls, int idx, dou
         else if (cls == OR_SPHERE) { c = D->sph_c + (size_t)idx * d; r = D->sph_r[idx]; }
         else { c = D->outer_c; r = D->outer_r; }
         double s = 0.0;
-        for (int i = 0; i < d; ++i) s += (x[i] - c[i]) * (x[i] - c[i]);
+        for (int i = 0; i < g; ++i) s += (x[i] - c[i]) * (x[i] - c[i]);
         double n = sqrt(s);
         if (n == 0.0) {
-            for (int i = 0; i < d; ++i) xbar[i] = c[i];
+            for (int i = 0; i < g; ++i) xbar[i] = c[i];
             xbar[0] = c[0] + r;
             return;
         }
-        for (int i = 0; i < d; ++i) xbar[i] = c[i] + r * (x[i] - c[i]) / n;
+        for (int i = 0; i < g; ++i) xbar[i] = c[i] + r * (x[i] - c[i]) / n;
         return;
     }
     if (cls == OR_BOX) {
         const double* c = D->box_c + (size_t)idx * d;
         const double* h = D->box_h + (size_t)idx * d;
         int inside = 1;
-        for (int i = 0; i < d; ++i)
+        for (int i = 0; i < g; ++i)
             if (fabs(x[i] - c[i]) > h[i]) inside = 0;
         if (!inside) {
-            for (int i = 0; i < d; ++i) {
+            for (int i = 0; i < g; ++i) {
                 double a = c[i] - h[i], b = c[i] + h[i];
                 xbar[i] = x[i] < a ? a : (x[i] > b ? b : x[i]);
             }
@@ -259,7 +272,7 @@ void or_closest_point(const or_domain* D, const double* x, int cls, int idx, dou
         /* inside: move the coordinate of the nearest face onto that face */
         int im = 0;
         double qm = -INFINITY;
-        for (int i = 0; i < d; ++i) {
+        for (int i = 0; i < g; ++i) {
             double q = fabs(x[i] - c[i]) - h[i];
             if (q > qm) { qm = q; im = i; }
         }
@@ -269,7 +282,7 @@ void or_closest_point(const or_domain* D, const double* x, int cls, int idx, dou
     /* outer box: the nearest face, lower face first on ties */
     int im = 0, hiface = 0;
     double m = INFINITY;
-    for (int i = 0; i < d; ++i) {
+    for (int i = 0; i < g; ++i) {
         double a = x[i] - D->lo[i], b = D->hi[i] - x[i];
         if (a < m) { m = a; im = i; hiface = 0; }
         if (b < m) { m = b; im = i; hiface = 1; }

@@ -56,11 +56,13 @@ def clear_mask(P, scene, delta, chunk=256):
     P = np.atleast_2d(np.asarray(P, dtype=np.float64))
     ok = np.ones(len(P), dtype=bool)
     o = scene["outer"]
+    k = int(scene.get("geom_d") or scene["d"])  # extruded geometry: leading k coordinates
     for i in range(0, len(P), chunk):
         p = P[i:i + chunk]
+        pg = p[:, :k]
         m = np.ones(len(p), dtype=bool)
         if scene["sph_r"].size:
-            sq = ((p[:, None, :] - scene["sph_c"][None]) ** 2).sum(axis=-1)
+            sq = ((pg[:, None, :] - scene["sph_c"][None, :, :k]) ** 2).sum(axis=-1)
             m &= ~(sq < (scene["sph_r"][None] + delta) ** 2).any(axis=1)
         if scene["box_h"].size:
             away = (np.abs(p[:, None, :] - scene["box_c"][None])
@@ -69,9 +71,9 @@ def clear_mask(P, scene, delta, chunk=256):
         if scene.get("goal_r") is not None:
             m &= ((p - scene["goal_c"]) ** 2).sum(axis=1) >= (scene["goal_r"] + delta) ** 2
         if o["kind"] == "box":
-            m &= np.all(p >= o["lo"] + delta, axis=1) & np.all(p <= o["hi"] - delta, axis=1)
+            m &= np.all(pg >= o["lo"][:k] + delta, axis=1) & np.all(pg <= o["hi"][:k] - delta, axis=1)
         else:
-            m &= ((p - o["c"]) ** 2).sum(axis=1) <= max(o["r"] - delta, 0.0) ** 2
+            m &= ((pg - o["c"][:k]) ** 2).sum(axis=1) <= max(o["r"] - delta, 0.0) ** 2
         ok[i:i + chunk] = m
     return ok
 
@@ -333,6 +335,55 @@ def scene_ball_source(d, R=1.0, sigma=1.0, eps=1e-4, queries=None, n_walks=4096,
     s["bdata"] = _bdata(0, d, g_goal=0.0, g_obs=0.0, g_outer=0.0)
     s["source"] = {"z": np.zeros(d), "amp": 1.0, "c_imp": 1.0}
     s["name"] = f"ball_src_d{d}"
+    return s
+
+
+def scene_eval_env(d, k_r=0.3, sigma=1.0, eps=1e-2, queries=None, n_walks=4096, seed=0,
+                   goal=(8.0, 0.0)):
+    """The paper's evaluation environment (Sec. VI): an outer disk of radius
+    r_o = 10 at the origin, an upper obstacle disk of radius r_u = k_r r_o and
+    a lower one of radius r_l = r_u / 2 whose circles touch only at the
+    origin, extruded: the geometry depends on (x_1, x_2) only and every
+    further coordinate is unbounded.  A unit impulse at the goal point with
+    zero boundary data; the goal point (8, 0) and the query x_start,1 = (-8, 0)
+    (extra coordinates 0) are read off the paper's figures."""
+    r_o = 10.0
+    r_u = k_r * r_o
+    r_l = 0.5 * r_u
+    c = np.zeros((2, d))
+    c[0, 1] = r_u
+    c[1, 1] = -r_l
+    s = {"sph_c": c, "sph_r": np.array([r_u, r_l]),
+         "box_c": np.zeros((0, d)), "box_h": np.zeros((0, d))}
+    z = np.zeros(d)
+    z[:2] = goal
+    if queries is None:
+        queries = np.zeros((1, d))
+        queries[0, 0] = -8.0
+    s.update(d=d, geom_d=2, goal_c=None, goal_r=None,
+             outer={"kind": "ball", "c": np.zeros(d), "r": r_o},
+             bdata=_bdata(0, d, g_goal=0.0, g_obs=0.0, g_outer=0.0),
+             source={"z": z, "amp": 1.0, "c_imp": 1.0},
+             sigma=float(sigma), eps=float(eps), queries=np.asarray(queries, float),
+             n_walks=n_walks, seed=seed, name=f"eval_env_d{d}_kr{k_r:g}")
+    return s
+
+
+def scene_extruded_annulus(d, r_in=0.5, r_out=2.0, sigma=0.0, eps=1e-4, queries=None,
+                           n_walks=4096, seed=0):
+    """An annulus in (x_1, x_2) extruded along every further coordinate: the
+    inner disk is an obstacle carrying g = 1, the outer circle carries g = 0.
+    The solution does not depend on the extra coordinates, so it is the
+    two-dimensional one for every d: ln(r_out / rho) / ln(r_out / r_in) at
+    sigma = 0, rho = |(x_1, x_2)|."""
+    s = {"sph_c": np.zeros((1, d)), "sph_r": np.array([float(r_in)]),
+         "box_c": np.zeros((0, d)), "box_h": np.zeros((0, d))}
+    s.update(d=d, geom_d=2, goal_c=None, goal_r=None,
+             outer={"kind": "ball", "c": np.zeros(d), "r": float(r_out)},
+             bdata=_bdata(0, d, g_goal=0.0, g_obs=1.0, g_outer=0.0),
+             sigma=float(sigma), eps=float(eps),
+             queries=np.zeros((1, d)) if queries is None else np.asarray(queries, float),
+             n_walks=n_walks, seed=seed, name=f"ext_annulus_d{d}")
     return s
 
 
