@@ -105,6 +105,14 @@ typedef struct {
     const double* hi;      /* host, d (box), hi > lo */
     const double* center;  /* host, d (ball) */
     double radius;         /* ball radius > 0 */
+    int geom_d;            /* 0 or d: the full space.  1 <= geom_d < d: extruded
+                              geometry (Sec. VI): the outer boundary and every
+                              obstacle depend on the first geom_d coordinates only
+                              and the remaining ones are unbounded; only the first
+                              geom_d entries of lo, hi, center and of the sphere
+                              centres are read.  The goal ball and the point
+                              source stay d-dimensional.  Box obstacles need the
+                              full space. */
 } wos_outer;
 
 typedef struct {
@@ -149,7 +157,8 @@ typedef struct {
  * obstacle, which changes the work done, never a distance or a walk.
  * source may be NULL (no volume source, the boundary-data problem).
  * Errors: WOS_EDIM, WOS_EINVAL (NULL out/outer/bdata, non-finite values,
- * negative radii, empty box, bad source), WOS_ENOMEM, WOS_EHIP.
+ * negative radii, empty box, bad source, geom_d outside [0, d], boxes with
+ * geom_d < d), WOS_ENOMEM, WOS_EHIP.
  */
 int wos_create_domain(int d, const wos_spheres* spheres, const wos_boxes* boxes,
                       const wos_ball* goal, const wos_outer* outer, const wos_bdata* bdata,

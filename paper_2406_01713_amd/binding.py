@@ -52,7 +52,7 @@ class Ball(C.Structure):
 
 class Outer(C.Structure):
     _fields_ = [("kind", C.c_int), ("lo", C.POINTER(C.c_double)), ("hi", C.POINTER(C.c_double)),
-                ("center", C.POINTER(C.c_double)), ("radius", C.c_double)]
+                ("center", C.POINTER(C.c_double)), ("radius", C.c_double), ("geom_d", C.c_int)]
 
 
 class BData(C.Structure):
@@ -175,12 +175,13 @@ class Domain:
             gc = arr(scene["goal_c"], (d,))
             goal = Ball(_dp(gc), float(scene["goal_r"]))
         o = scene["outer"]
+        gd = int(scene.get("geom_d") or 0)  # 0: the full space
         if o["kind"] == "box":
             lo, hi = arr(o["lo"], (d,)), arr(o["hi"], (d,))
-            outer = Outer(WOS_OUTER_BOX, _dp(lo), _dp(hi), None, 0.0)
+            outer = Outer(WOS_OUTER_BOX, _dp(lo), _dp(hi), None, 0.0, gd)
         else:
             oc = arr(o["c"], (d,))
-            outer = Outer(WOS_OUTER_BALL, None, None, _dp(oc), float(o["r"]))
+            outer = Outer(WOS_OUTER_BALL, None, None, _dp(oc), float(o["r"]), gd)
         b = scene["bdata"]
         ak = arr(b["ak"], (d,))
         bd = BData(int(b["mode"]), float(b["g_goal"]), float(b["g_obs"]), float(b["g_outer"]),

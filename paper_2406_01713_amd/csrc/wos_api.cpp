@@ -28,6 +28,10 @@ namespace {
 
 thread_local std::string g_err;
 
+// Outer-box faces of unbounded coordinates (extruded geometry): far enough
+// never to be the nearest face, finite in FP32.
+constexpr double kFarFace = 1e30;
+
 int fail(int code, const char* fmt, ...)
 {
     char buf[512];
@@ -61,6 +65,7 @@ bool finite_all(const double* p, int64_t n)
 
 struct wos_domain {
     int d = 0;
+    int geom_d = 0;  // obstacles and the outer boundary use the first geom_d coordinates
     int device = 0;
     int64_t n_sph = 0, n_box = 0;
     float* sph_f = nullptr;
@@ -153,6 +158,8 @@ int make_env(const wos_domain* D, double sigma, double eps, uint64_t seed, uint3
     p.box_mf = D->cl_f ? D->cl_f + D->off_box_mf : nullptr;
     p.use_mfma = (sizeof(T) == 4 && !(o.flags & WOS_SCALAR_CULL)) ? 1 : 0;
     p.d = D->d;
+    p.geom_d = D->geom_d;
+    p.pad_g = 0;
     p.has_goal = D->has_goal ? 1 : 0;
     p.outer_kind = D->outer_kind;
     p.mode = D->mode;
@@ -407,12 +414,13 @@ int64_t cluster_order(int d, int64_t n, const double* centers, std::vector<int64
 }
 
 // Matrix-core cluster features (see kMfmaTile) from the FP32 bound rows:
-// out holds ceil(n_cl / 16) tiles of 64 x 4 floats.
+// out holds ceil(n_cl / 16) + 1 tiles of 64 x 4 floats, the last a spare
+// all-skip tile that the kernel reads ahead into and never tests.
 void build_mfma_features(int d, int64_t n_cl, const float* bnd, float* out)
 {
     const int SB = sph_stride(d);
     const double m = 0x1p-12;
-    const int64_t n_tiles = (n_cl + kMfmaTile - 1) / kMfmaTile;
+    const int64_t n_tiles = (n_cl + kMfmaTile - 1) / kMfmaTile + 1;  // + the spare tile
     for (int64_t t = 0; t < n_tiles; ++t)
         for (int lane = 0; lane < 64; ++lane) {
             const int j = lane % kMfmaTile, k = lane / kMfmaTile;
@@ -768,8 +776,24 @@ int wos_create_domain(int d, const wos_spheres* spheres, const wos_boxes* boxes,
         return fail(WOS_EINVAL, "bad point source (z NULL or non-finite, amplitude non-finite, c_imp < 0)");
     if (bdata->mode != 0 && !bdata->a_or_k) return fail(WOS_EINVAL, "a_or_k is required for mode %d", bdata->mode);
 
+    const int gd = outer->geom_d == 0 ? d : outer->geom_d;
+    if (gd < 1 || gd > d) return fail(WOS_EINVAL, "geom_d = %d outside [0, %d]", outer->geom_d, d);
+    if (gd < d && nb > 0) return fail(WOS_EINVAL, "box obstacles need the full space (geom_d = d)");
+    // extruded geometry: sphere centres without their trailing coordinates
+    std::vector<double> sc_ext;
+    wos_spheres sph_ext;
+    if (gd < d && ns > 0) {
+        sc_ext.assign(spheres->centers, spheres->centers + ns * d);
+        for (int64_t j = 0; j < ns; ++j)
+            for (int i = gd; i < d; ++i) sc_ext[j * d + i] = 0.0;
+        sph_ext = *spheres;
+        sph_ext.centers = sc_ext.data();
+        spheres = &sph_ext;
+    }
+
     wos_domain* D = new wos_domain();
     D->d = d;
+    D->geom_d = gd;
     D->n_sph = ns;
     D->n_box = nb;
     if (goal) {
@@ -783,12 +807,12 @@ int wos_create_domain(int d, const wos_spheres* spheres, const wos_boxes* boxes,
     }
     D->outer_kind = outer->kind;
     if (outer->kind == WOS_OUTER_BOX) {
-        if (!outer->lo || !outer->hi || !finite_all(outer->lo, d) || !finite_all(outer->hi, d)) {
+        if (!outer->lo || !outer->hi || !finite_all(outer->lo, gd) || !finite_all(outer->hi, gd)) {
             delete D;
             return fail(WOS_EINVAL, "bad outer box");
         }
         double rmax = INFINITY;
-        for (int i = 0; i < d; ++i) {
+        for (int i = 0; i < gd; ++i) {
             if (!(outer->hi[i] > outer->lo[i])) {
                 delete D;
                 return fail(WOS_EINVAL, "outer box needs hi > lo");
@@ -797,13 +821,19 @@ int wos_create_domain(int d, const wos_spheres* spheres, const wos_boxes* boxes,
             D->hi[i] = outer->hi[i];
             rmax = std::min(rmax, 0.5 * (outer->hi[i] - outer->lo[i]));
         }
+        // unbounded trailing coordinates: the kernels see them as 0, so these
+        // faces are never the nearest
+        for (int i = gd; i < d; ++i) {
+            D->lo[i] = -kFarFace;
+            D->hi[i] = kFarFace;
+        }
         D->r_max = rmax;
     } else if (outer->kind == WOS_OUTER_BALL) {
-        if (!outer->center || !(outer->radius > 0) || !finite_all(outer->center, d) || !std::isfinite(outer->radius)) {
+        if (!outer->center || !(outer->radius > 0) || !finite_all(outer->center, gd) || !std::isfinite(outer->radius)) {
             delete D;
             return fail(WOS_EINVAL, "bad outer ball");
         }
-        for (int i = 0; i < d; ++i) D->oc[i] = outer->center[i];
+        for (int i = 0; i < gd; ++i) D->oc[i] = outer->center[i];
         D->orad = outer->radius;
         D->r_max = outer->radius;
     } else {
@@ -856,8 +886,9 @@ int wos_create_domain(int d, const wos_spheres* spheres, const wos_boxes* boxes,
     D->off_box_bnd = D->off_box_cl + (size_t)D->n_cl_box * kCluster * bs;
     const size_t cl_elems = D->off_box_bnd + nbb * sb;
     // matrix-core features live in the FP32 buffer only, after the tables
-    const size_t mf_s = (size_t)((D->n_cl_sph + kMfmaTile - 1) / kMfmaTile) * 64 * 4;
-    const size_t mf_b = (size_t)((D->n_cl_box + kMfmaTile - 1) / kMfmaTile) * 64 * 4;
+    // one spare tile after each table: the kernel loads tile t + 1 while testing tile t
+    const size_t mf_s = D->n_cl_sph ? (size_t)((D->n_cl_sph + kMfmaTile - 1) / kMfmaTile + 1) * 64 * 4 : 0;
+    const size_t mf_b = D->n_cl_box ? (size_t)((D->n_cl_box + kMfmaTile - 1) / kMfmaTile + 1) * 64 * 4 : 0;
     D->off_sph_mf = (cl_elems + 3) / 4 * 4;  // 16-byte aligned float4 rows
     D->off_box_mf = D->off_sph_mf + mf_s;
     const size_t cf_elems = D->off_box_mf + mf_b;

@@ -381,8 +381,12 @@ __device__ __forceinline__ float cluster_min_mfma(cptr<float> rows, const float*
     const mf4* tab = reinterpret_cast<const mf4*>(mf) + (threadIdx.x & (kWave - 1));
     const int n_tiles = (n_cl + kMfmaTile - 1) / kMfmaTile;
     float best = Math<float>::inf();
+    // the next tile's features load while this tile is tested (the table
+    // ends with a spare tile that is never used)
+    mf4 bn = tab[0];
     for (int t = 0; t < n_tiles; ++t) {
-        const mf4 b = tab[t * kWave];
+        const mf4 b = bn;
+        bn = tab[(t + 1) * kWave];
         uint64_t keep = 0;
 #pragma unroll
         for (int rt = 0; rt < 4; ++rt) {
@@ -433,7 +437,12 @@ __device__ __forceinline__ T distance(cenv<T> p, const T (&x)[D], int& cls, Work
         }
         dg = Math<T>::sqrt(acc) - p->goal_r;
     }
-    const T dout = outer_dist<T, D>(fresh(p), x);
+    // extruded geometry: obstacles and the outer boundary see the leading
+    // geom_d coordinates only (their stored centres are zero beyond them)
+    T xg[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) xg[i] = (i < p->geom_d) ? x[i] : T(0);
+    const T dout = outer_dist<T, D>(fresh(p), xg);
     p = fresh(p);
     T db;
     uint32_t nb, ns;
@@ -442,16 +451,16 @@ __device__ __forceinline__ T distance(cenv<T> p, const T (&x)[D], int& cls, Work
         bool done = false;
         if constexpr (sizeof(T) == 4) {
             if (p->use_mfma) {
-                db = cluster_min_mfma<D, true>(to_const(p->box_cl), fresh(p)->box_mf, fresh(p)->n_cl_box, x,
+                db = cluster_min_mfma<D, true>(to_const(p->box_cl), fresh(p)->box_mf, fresh(p)->n_cl_box, xg,
                                                Math<T>::min(dg, dout), live, nb);
                 done = true;
             }
         }
         if (!done)
-            db = cluster_min<T, D, true>(to_const(fresh(p)->box_cl), to_const(fresh(p)->box_bnd), fresh(p)->n_cl_box, x,
+            db = cluster_min<T, D, true>(to_const(fresh(p)->box_cl), to_const(fresh(p)->box_bnd), fresh(p)->n_cl_box, xg,
                                          Math<T>::min(dg, dout), live, nb);
     } else {
-        db = boxes_min<T, D>(to_const(p->box), fresh(p)->n_box, x);
+        db = boxes_min<T, D>(to_const(p->box), fresh(p)->n_box, xg);
         nb = (uint32_t)fresh(p)->n_box;
     }
     p = fresh(p);
@@ -461,16 +470,16 @@ __device__ __forceinline__ T distance(cenv<T> p, const T (&x)[D], int& cls, Work
         bool done = false;
         if constexpr (sizeof(T) == 4) {
             if (p->use_mfma) {
-                ds = cluster_min_mfma<D, false>(to_const(p->sph_cl), fresh(p)->sph_mf, fresh(p)->n_cl_sph, x,
+                ds = cluster_min_mfma<D, false>(to_const(p->sph_cl), fresh(p)->sph_mf, fresh(p)->n_cl_sph, xg,
                                                 Math<T>::min(Math<T>::min(dg, dout), db), live, ns);
                 done = true;
             }
         }
         if (!done)
             ds = cluster_min<T, D, false>(to_const(fresh(p)->sph_cl), to_const(fresh(p)->sph_bnd), fresh(p)->n_cl_sph,
-                                          x, Math<T>::min(Math<T>::min(dg, dout), db), live, ns);
+                                          xg, Math<T>::min(Math<T>::min(dg, dout), db), live, ns);
     } else {
-        ds = spheres_min<T, D>(to_const(p->sph), fresh(p)->n_sph, x);
+        ds = spheres_min<T, D>(to_const(p->sph), fresh(p)->n_sph, xg);
         ns = (uint32_t)fresh(p)->n_sph;
     }
     const uint64_t lanes = (uint64_t)__popcll(__ballot(live));
@@ -482,10 +491,11 @@ __device__ __forceinline__ T distance(cenv<T> p, const T (&x)[D], int& cls, Work
     return Math<T>::min(dg, rest);
 }
 
-// Closest boundary point xbar on the absorbing component (Fig. 2).  Sphere and
-// box indices are recovered by rescanning with the same distance code.
+// Closest boundary point xbar on the absorbing component (Fig. 2), in the
+// coordinates the component depends on.  Sphere and box indices are
+// recovered by rescanning with the same distance code.
 template <typename T, int D>
-__device__ __forceinline__ void closest_point(cenv<T> p, const T (&x)[D], int cls, T (&xb)[D])
+__device__ __forceinline__ void closest_point_in(cenv<T> p, const T (&x)[D], int cls, T (&xb)[D])
 {
 #pragma unroll
     for (int i = 0; i < D; ++i) xb[i] = x[i];
@@ -569,6 +579,22 @@ __device__ __forceinline__ void closest_point(cenv<T> p, const T (&x)[D], int cl
     const T s = r / Math<T>::sqrt(n2);
 #pragma unroll
     for (int i = 0; i < D; ++i) xb[i] = c[i] + s * (x[i] - c[i]);
+}
+
+// Closest boundary point of an extruded component (obstacle or outer
+// boundary with geom_d < d): the projection acts on the leading geom_d
+// coordinates and keeps the others.
+template <typename T, int D>
+__device__ __forceinline__ void closest_point(cenv<T> p, const T (&x)[D], int cls, T (&xb)[D])
+{
+    const int k = (cls == kGoal) ? D : p->geom_d;
+    T xg[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) xg[i] = (i < k) ? x[i] : T(0);
+    closest_point_in<T, D>(p, xg, cls, xb);
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+        if (i >= k) xb[i] = x[i];
 }
 
 // Boundary data g at the closest point of the absorbing component.

@@ -42,7 +42,8 @@ constexpr int kClusterMin = 64;
 // features are stored per tile of 16 clusters as 64 lanes x 4 floats: lane
 // j + 16 k holds features k, 4 + k, 8 + k of cluster j of the tile (the B
 // operand of three 16x16x4 products), the 4th float unused.  Padding
-// clusters of the last tile have feature 9 = 1e30 (always skipped).
+// clusters of the last tile, and one spare tile after it, have feature
+// 9 = 1e30 (always skipped).
 constexpr int kMfmaTile = 16;
 constexpr int kMfmaFeat = 12;
 
@@ -56,12 +57,13 @@ struct EnvP {
     const T* box_cl;       // n_cl_box x kCluster box rows, cluster order
     const T* sph_bnd;      // n_cl_sph + 1 bounding spheres, sph_stride(d) each (last: unused)
     const T* box_bnd;      // n_cl_box + 1 bounding spheres, sph_stride(d) each (last: unused)
-    const float* sph_mf;   // matrix-core cluster features, ceil(n_cl_sph / 16) x 64 x 4 (FP32 only)
+    const float* sph_mf;   // matrix-core cluster features, (ceil(n_cl_sph / 16) + 1) x 64 x 4 (FP32 only)
     const float* box_mf;
     int32_t n_sph, n_box;
     int32_t n_cl_sph, n_cl_box;  // 0: scan the caller-order table instead
     int32_t use_mfma, pad_mf;    // 1: cluster tests on the matrix cores (FP32 kernels)
     int32_t d, has_goal;
+    int32_t geom_d, pad_g;     // obstacles and the outer boundary depend on x[0..geom_d) only
     int32_t outer_kind, mode;  // outer: 0 box, 1 ball; mode: 0 class, 1 affine, 2 plane
     int32_t nt_C, nt_C1;       // Horner terms of 0F1(;d/2;y) and 0F1(;d/2+1;y)
     uint32_t key0, key1;       // Philox key (seed)

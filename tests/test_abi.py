@@ -85,6 +85,31 @@ def test_create_domain_rejects_bad_obstacles(B):
     assert B.lib.wos_create_domain(d, None, None, None, C.byref(ob), C.byref(bd), None, C.byref(h)) == B.WOS_EINVAL
 
 
+def test_create_domain_rejects_bad_extrusion(B):
+    """geom_d outside [0, d] and box obstacles in extruded geometry are
+    rejected before any device call."""
+    d = 3
+    h = C.c_void_p()
+    bd = _bdata(B)
+    oc = np.zeros(d)
+    for gd in (-1, 4, 9):
+        ob = B.Outer(B.WOS_OUTER_BALL, None, None, oc.ctypes.data_as(C.POINTER(C.c_double)), 2.0, gd)
+        assert B.lib.wos_create_domain(d, None, None, None, C.byref(ob), C.byref(bd), None, C.byref(h)) == B.WOS_EINVAL
+        assert b"geom_d" in B.lib.wos_last_error()
+    ob = B.Outer(B.WOS_OUTER_BALL, None, None, oc.ctypes.data_as(C.POINTER(C.c_double)), 2.0, 2)
+    bc = np.zeros((1, d))
+    bh = np.full((1, d), 0.1)
+    bx = B.Boxes(1, bc.ctypes.data_as(C.POINTER(C.c_double)), bh.ctypes.data_as(C.POINTER(C.c_double)))
+    assert B.lib.wos_create_domain(d, None, C.byref(bx), None, C.byref(ob), C.byref(bd), None, C.byref(h)) == B.WOS_EINVAL
+    assert b"full space" in B.lib.wos_last_error()
+    # an outer box whose bounds are only given for the leading coordinates
+    lo = np.array([-1.0, -1.0, np.nan])
+    hi = np.array([1.0, 1.0, np.nan])
+    ob2 = B.Outer(B.WOS_OUTER_BOX, lo.ctypes.data_as(C.POINTER(C.c_double)),
+                  hi.ctypes.data_as(C.POINTER(C.c_double)), None, 0.0, 3)
+    assert B.lib.wos_create_domain(d, None, None, None, C.byref(ob2), C.byref(bd), None, C.byref(h)) == B.WOS_EINVAL
+
+
 def test_calls_reject_null_handles(B):
     assert B.lib.wos_estimate(None, None, 1, 16, 1.0, 1e-3, 0, None, None, None, None, None) == B.WOS_EINVAL
     assert B.lib.wos_backward(None, None, 1, 16, 1.0, 1e-3, 0, None, None, None, None, None, None,
