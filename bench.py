@@ -263,6 +263,69 @@ def planning(B, torch, n_steps, near_goal=False, source=False):
     return res
 
 
+def eval_env_sweep(B, torch, dims=(2, 3, 4, 5), ns=(10 ** 3, 10 ** 4, 10 ** 5, 10 ** 6), reps=32):
+    """The paper's dimensionality study (Sec. VI): in the evaluation
+    environment (k_r = 0.3, c = 1, eps = 0.01, unit impulse at the goal
+    point (8, 0), free extra coordinates 0), the angle between the gradient
+    estimated with n walks and a reference gradient from many more walks, at
+    x_start,1 = (-8, 0) (behind the obstacle: few walks reach the source) and
+    at (5, 3.5) (in view of the goal); reps independent estimates per n
+    (distinct query indices of one launch draw independent walks), the share
+    of them with any signal, and the time of one single-query estimate."""
+    from paper_2406_01713_amd import scenes as S
+    points = {"x_start_1": ((-8.0, 0.0), 10 ** 9), "in_view": ((5.0, 3.5), 10 ** 8)}
+    out = {"k_r": 0.3, "sigma": 1.0, "eps": 0.01, "goal": "unit impulse at (8, 0, 0, ...)", "reps": reps,
+           "points": {k: {"x": list(v[0]), "reference_walks": v[1]} for k, v in points.items()}, "by_d": {}}
+    st = torch.cuda.current_stream()
+    for d in dims:
+        s = S.scene_eval_env(d, k_r=0.3, sigma=1.0, eps=1e-2)
+        dom = B.Domain(s)
+        rd = {}
+        for name, (p2, n_ref) in points.items():
+            xp = np.zeros((1, d))
+            xp[0, :2] = p2
+            x = torch.as_tensor(xp, dtype=torch.float32, device="cuda")
+            u1 = torch.empty(1, device="cuda")
+            g1 = torch.empty(1, d, device="cuda")
+            t = time.perf_counter()
+            B.wos_estimate(dom, x, n_ref, s["sigma"], s["eps"], 987654321, u1, g1)
+            torch.cuda.synchronize()
+            t_ref = time.perf_counter() - t
+            gt = g1.cpu().numpy()[0].astype(np.float64)
+            xr = x.repeat(reps, 1).contiguous()
+            ur = torch.empty(reps, device="cuda")
+            gr = torch.empty(reps, d, device="cuda")
+            err, sig, ms = {}, {}, {}
+            for n in ns:
+                B.wos_estimate(dom, xr, n, s["sigma"], s["eps"], 1, ur, gr)
+                ge = gr.cpu().numpy().astype(np.float64)
+                nz = np.linalg.norm(ge, axis=1) > 0
+                cosv = (ge @ gt) / np.maximum(np.linalg.norm(ge, axis=1) * np.linalg.norm(gt), 1e-300)
+                ang = np.degrees(np.arccos(np.clip(cosv, -1.0, 1.0)))
+                ang[~nz] = 90.0  # no walk reached the source: no direction
+                err[str(n)] = float(ang.mean())
+                sig[str(n)] = float(nz.mean())
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                B.wos_estimate(dom, x, n, s["sigma"], s["eps"], 2, u1, g1)
+                e0.record(st)
+                for _ in range(5):
+                    B.wos_estimate(dom, x, n, s["sigma"], s["eps"], 2, u1, g1)
+                e1.record(st)
+                torch.cuda.synchronize()
+                ms[str(n)] = e0.elapsed_time(e1) / 5
+            lx = np.log10(np.array(ns, dtype=np.float64))
+            ly = np.log10(np.array([err[str(n)] for n in ns]))
+            rd[name] = {"mean_angle_error_deg": err, "share_with_signal": sig, "ms_per_estimate": ms,
+                        "log_log_slope": float(np.polyfit(lx, ly, 1)[0]),
+                        "reference_grad_nonzero": bool(np.linalg.norm(gt) > 0), "reference_s": t_ref}
+            log(f"eval env d={d} {name}: angle error (deg) "
+                + ", ".join(f"n={n}: {err[str(n)]:.2f}" for n in ns)
+                + f"; signal {sig[str(ns[0])]:.2f}..{sig[str(ns[-1])]:.2f}; reference {t_ref:.1f} s")
+        out["by_d"][str(d)] = rd
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -275,6 +338,8 @@ def main():
     ap.add_argument("--no-plan", action="store_true")
     ap.add_argument("--no-se", action="store_true")
     ap.add_argument("--no-source", action="store_true", help="skip the point-source workload")
+    ap.add_argument("--no-eval-env", action="store_true",
+                    help="skip the evaluation-environment dimension sweep")
     ap.add_argument("--only-batched", action="store_true", help="time the batched step only (profiling)")
     ap.add_argument("--plan-steps", type=int, default=200)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -285,7 +350,7 @@ def main():
               "(multi-GPU sharding is described in DESIGN.md, not run). Use --gpus 1.", file=sys.stderr)
         sys.exit(2)
     if args.only_batched:
-        args.no_plain = args.no_cpu = args.no_plan = args.no_se = args.no_source = True
+        args.no_plain = args.no_cpu = args.no_plan = args.no_se = args.no_source = args.no_eval_env = True
 
     t = time.perf_counter()
     envs = workload()
@@ -494,6 +559,11 @@ def main():
             log(f"planning to a point source: {out['planning_d7_point_source']['arrived']} / "
                 f"{out['planning_d7_point_source_near_goal']['arrived']} arrived "
                 f"({time.perf_counter() - t:.1f} s)")
+
+    if not args.no_eval_env:
+        t = time.perf_counter()
+        out["eval_env_dim_sweep"] = eval_env_sweep(B, torch)
+        log(f"evaluation-environment sweep ({time.perf_counter() - t:.1f} s)")
 
     if cpu is not None:
         out["cpu_baseline"] = cpu

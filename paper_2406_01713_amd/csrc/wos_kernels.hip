@@ -180,16 +180,35 @@ finalize_plain(const double* __restrict__ partials, int64_t n_q, int32_t chunks,
                const T* __restrict__ ubar, T* __restrict__ out_dx, double* __restrict__ out_dq,
                double* __restrict__ prod)
 {
-    const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    // one block per query: thread t sums chunks t, t + kBlock, ... in order,
+    // then a butterfly over each wave and the waves in index order, so the
+    // result does not depend on timing
+    const int64_t q = blockIdx.x;
     if (q >= n_q) return;
     constexpr int NA = nacc(D);
+    constexpr int NW = kBlock / kWave;
+    __shared__ double wsum[NW][NA];
     double a[NA];
 #pragma unroll
     for (int i = 0; i < NA; ++i) a[i] = 0.0;
     const double* row = partials + q * chunks * NA;
-    for (int c = 0; c < chunks; ++c) {
+    for (int c = threadIdx.x; c < chunks; c += kBlock) {
 #pragma unroll
-        for (int i = 0; i < NA; ++i) a[i] += row[c * NA + i];
+        for (int i = 0; i < NA; ++i) a[i] += row[(int64_t)c * NA + i];
+    }
+#pragma unroll
+    for (int i = 0; i < NA; ++i) a[i] = wave_sum(a[i]);
+    const int wv = threadIdx.x / kWave;
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+#pragma unroll
+        for (int i = 0; i < NA; ++i) wsum[wv][i] = a[i];
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+        a[i] = wsum[0][i];
+        for (int w = 1; w < NW; ++w) a[i] += wsum[w][i];
     }
     const double n = (double)n_walks;
     out_u[q] = (T)(a[0] / n);
@@ -619,7 +638,7 @@ static hipError_t fin_d(bool bwd, const double* partials, int64_t n_q, int32_t c
                         double* out_dq, double* prod, hipStream_t st)
 {
     if (n_q == 0) return hipSuccess;
-    const unsigned grid = blocks_for(n_q, kBlock);
+    const unsigned grid = (unsigned)n_q;  // one block per query
     if (bwd)
         hipLaunchKernelGGL((finalize_plain<T, D, true>), dim3(grid), dim3(kBlock), 0, st, partials, n_q,
                            chunks, n_walks, out_u, out_grad, out_stats, ubar, out_dx, out_dq, prod);
