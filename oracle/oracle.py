@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "wos_oracle.c")
 LIB = os.path.join(HERE, "libwos_oracle.so")
 MAXD = 8
-GOAL, SPHERE, BOX, OUTER = 0, 1, 2, 3
+GOAL, SPHERE, BOX, OUTER, ARM = 0, 1, 2, 3, 4
 ABSORBED, DEGENERATE, TRUNCATED = 0, 1, 2
 DEFAULT_MAX_STEPS = 1 << 16
 
@@ -40,6 +40,7 @@ class OrDomain(C.Structure):
         ("mode", C.c_int), ("g_goal", C.c_double), ("g_obs", C.c_double),
         ("g_outer", C.c_double), ("ak", C.c_double * MAXD), ("b", C.c_double),
         ("geom_d", C.c_int),
+        ("n_arm", C.c_int), ("arm_pts", C.POINTER(C.c_double)), ("arm_l", C.c_double * MAXD),
     ]
 
 
@@ -67,6 +68,10 @@ def lib():
         L.or_distance.argtypes = [C.POINTER(OrDomain), dp, C.POINTER(C.c_int), C.POINTER(C.c_int)]
         L.or_distance.restype = C.c_double
         L.or_closest_point.argtypes = [C.POINTER(OrDomain), dp, C.c_int, C.c_int, dp]
+        L.or_arm_K.argtypes = [C.POINTER(OrDomain)]
+        L.or_arm_K.restype = C.c_double
+        L.or_arm_task_distance.argtypes = [C.POINTER(OrDomain), dp]
+        L.or_arm_task_distance.restype = C.c_double
         L.or_boundary_value.argtypes = [C.POINTER(OrDomain), dp, C.c_int, C.c_int]
         L.or_boundary_value.restype = C.c_double
         for f in ("or_screening_C", "or_screening_C1", "or_dlnC_dsigma"):
@@ -132,6 +137,13 @@ class Domain:
                 D.goal_c[i] = float(scene["goal_c"][i])
             D.goal_r = float(scene["goal_r"])
         D.geom_d = int(scene.get("geom_d") or 0)  # 0: the full space
+        arm = scene.get("arm")
+        if arm is not None:
+            ap = arr(arm["pts"], (-1, 2))
+            D.n_arm = len(ap)
+            D.arm_pts = _dp(ap)
+            for i in range(d):
+                D.arm_l[i] = float(arm["l"][i])
         o = scene["outer"]
         if o["kind"] == "box":
             D.outer_kind = 0
@@ -195,6 +207,17 @@ def closest_point(scene_or_dom, x, cls, idx):
     out = np.zeros(dom.d)
     lib().or_closest_point(dom.ref, _dp(x), cls, idx, _dp(out))
     return out
+
+
+def arm_K(scene_or_dom):
+    dom = scene_or_dom if isinstance(scene_or_dom, Domain) else Domain(scene_or_dom)
+    return lib().or_arm_K(dom.ref)
+
+
+def arm_task_distance(scene_or_dom, q):
+    dom = scene_or_dom if isinstance(scene_or_dom, Domain) else Domain(scene_or_dom)
+    q = np.ascontiguousarray(np.asarray(q, dtype=np.float64))
+    return lib().or_arm_task_distance(dom.ref, _dp(q))
 
 
 def boundary_value(scene_or_dom, x, cls, idx):

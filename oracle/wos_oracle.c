@@ -39,6 +39,11 @@
  *       grad_hat u(x_0) = (d / R_0) C1(R_0) u_hat(x_1) v_0
  *                         + c_imp amp grad_x G_B(x_0, z) 1{|z - x_0| < R_0},
  *   with u_hat(x_1) the same sum over the walk from x_1 (weights W1_k).
+ *   Planar arm (Sec. V-B): with joint coordinates q and task-space obstacle
+ *   points, the joint-space distance to collision is replaced by the lower
+ *   bound d_tau(q) / K, d_tau the planar distance between the points and the
+ *   arm's links and K a Lipschitz constant of the planar forward kinematics
+ *   (see or_arm_K); ties order goal, spheres, boxes, arm, outer.
  *   Extruded geometry (Sec. VI, the evaluation environment): the obstacles
  *   and the outer boundary may depend on the first geom_d coordinates only,
  *   the others being unbounded; their distances and closest points are then
@@ -59,7 +64,7 @@
 #define OR_MAXD 8
 #define OR_PI 3.14159265358979323846
 
-enum { OR_GOAL = 0, OR_SPHERE = 1, OR_BOX = 2, OR_OUTER = 3 };
+enum { OR_GOAL = 0, OR_SPHERE = 1, OR_BOX = 2, OR_OUTER = 3, OR_ARM = 4 };
 enum { OR_ABSORBED = 0, OR_DEGENERATE = 1, OR_TRUNCATED = 2 };
 
 typedef struct {
@@ -86,6 +91,9 @@ typedef struct {
     double b;
     int geom_d; /* 0 or d: full space; else obstacles and the outer boundary
                    depend on x[0..geom_d) only (extruded, Sec. VI) */
+    int n_arm;              /* task-space obstacle points of a planar arm, 0: none */
+    const double* arm_pts;  /* n_arm x 2 */
+    double arm_l[OR_MAXD];  /* link lengths, one link per joint coordinate */
 } or_domain;
 
 typedef struct {
@@ -207,6 +215,47 @@ static double dist_outer(const or_domain* D, const double* x)
     return D->outer_r - sqrt(s);
 }
 
+/* Lipschitz constant of the planar forward kinematics (Sec. V-B): joint n
+ * moves every point beyond it at most (l_n + ... + l_N) per radian, so the
+ * Jacobian of any point of the arm has Frobenius norm at most
+ * K = sqrt(sum_n (l_n + ... + l_N)^2).  (The printed sum runs over the first
+ * n links; the two agree for equal links.) */
+double or_arm_K(const or_domain* D)
+{
+    double s = 0.0;
+    for (int n = 0; n < D->d; ++n) {
+        double reach = 0.0;
+        for (int i = n; i < D->d; ++i) reach += D->arm_l[i];
+        s += reach * reach;
+    }
+    return sqrt(s);
+}
+
+/* Planar distance between the obstacle points and the arm at joint angles q:
+ * the base joint sits at the origin, link i ends l_i further along the
+ * direction q_0 + ... + q_i; each link is a segment. */
+double or_arm_task_distance(const or_domain* D, const double* q)
+{
+    double ax = 0.0, ay = 0.0, th = 0.0, best = INFINITY;
+    for (int i = 0; i < D->d; ++i) {
+        th += q[i];
+        double bx = ax + D->arm_l[i] * cos(th), by = ay + D->arm_l[i] * sin(th);
+        double sx = bx - ax, sy = by - ay, ss = sx * sx + sy * sy;
+        for (int j = 0; j < D->n_arm; ++j) {
+            double px = D->arm_pts[2 * j] - ax, py = D->arm_pts[2 * j + 1] - ay;
+            double t = ss > 0.0 ? (px * sx + py * sy) / ss : 0.0;
+            if (t < 0.0) t = 0.0;
+            if (t > 1.0) t = 1.0;
+            double ex = px - t * sx, ey = py - t * sy;
+            double dist = sqrt(ex * ex + ey * ey);
+            if (dist < best) best = dist;
+        }
+        ax = bx;
+        ay = by;
+    }
+    return best;
+}
+
 double or_distance(const or_domain* D, const double* x, int* cls, int* idx)
 {
     int d = D->d, g = geom_dim(D);
@@ -224,6 +273,10 @@ double or_distance(const or_domain* D, const double* x, int* cls, int* idx)
         double dj = dist_box_signed(g, x, D->box_c + (size_t)j * d, D->box_h + (size_t)j * d);
         if (dj < best) { best = dj; bc = OR_BOX; bi = j; }
     }
+    if (D->n_arm > 0) {
+        double da = or_arm_task_distance(D, x) / or_arm_K(D);
+        if (da < best) { best = da; bc = OR_ARM; bi = 0; }
+    }
     double dout = dist_outer(D, x);
     if (dout < best) { best = dout; bc = OR_OUTER; bi = 0; }
     if (cls) *cls = bc;
@@ -239,6 +292,10 @@ void or_closest_point(const or_domain* D, const double* x, int cls, int idx, dou
     /* an extruded component moves the first g coordinates, keeps the rest */
     int g = cls == OR_GOAL ? d : geom_dim(D);
     memcpy(xbar, x, sizeof(double) * (size_t)d);
+    if (cls == OR_ARM) {  /* the bound names no boundary point */
+        for (int i = 0; i < d; ++i) xbar[i] = NAN;
+        return;
+    }
     if (cls == OR_GOAL || cls == OR_SPHERE || (cls == OR_OUTER && D->outer_kind == 1)) {
         const double* c;
         double r;

@@ -387,6 +387,60 @@ def scene_extruded_annulus(d, r_in=0.5, r_out=2.0, sigma=0.0, eps=1e-4, queries=
     return s
 
 
+RR_LINKS = (1.0, 1.0)  # link lengths: not given in the paper (unit links)
+RR_X_OBS = (0.0, 1.3)  # task-space point obstacle (Table II)
+RR_Q_LO = (-0.5 * PI, -PI)  # joint lower bounds: not given (each joint spans 2 pi)
+RR_Q_HI = (1.5 * PI, PI)  # joint upper bounds q_ub (Table II)
+RR_Q_START = (0.785, 0.800)
+RR_Q_GOAL = (2.042, 0.200)
+
+
+def rr_collision_points(links=RR_LINKS, x_obs=RR_X_OBS, n_col=200, n_dense=200001):
+    """N_col points, equally spaced in arc length, on the set of RR joint
+    configurations whose second link passes through the task-space point
+    x_obs (Sec. VII, IK-based distance): with the point at distance t along
+    link 2, the elbow angle q2 and the law of cosines give
+    t = -l1 cos q2 + sqrt(rho^2 - l1^2 sin^2 q2), q1 = atan2(x_obs) -
+    atan2(t sin q2, l1 + t cos q2), for |q2| up to the angle where t = l2.
+    Link 1 cannot touch the point (l1 < |x_obs|)."""
+    l1, l2 = links
+    rho = math.hypot(*x_obs)
+    if not (l1 < rho <= l1 + l2):
+        raise ValueError("the point must lie beyond link 1 and within reach")
+    a = math.acos((rho * rho - l1 * l1 - l2 * l2) / (2 * l1 * l2))
+    q2 = np.linspace(-a, a, n_dense)
+    t = -l1 * np.cos(q2) + np.sqrt(rho * rho - (l1 * np.sin(q2)) ** 2)
+    q1 = math.atan2(x_obs[1], x_obs[0]) - np.arctan2(t * np.sin(q2), l1 + t * np.cos(q2))
+    P = np.stack([q1, q2], axis=1)
+    s = np.concatenate([[0.0], np.cumsum(np.linalg.norm(np.diff(P, axis=0), axis=1))])
+    tgt = np.linspace(0.0, s[-1], n_col)
+    return np.stack([np.interp(tgt, s, q1), np.interp(tgt, s, q2)], axis=1)
+
+
+def scene_rr(distance="ik", sigma=0.0, n_walks=100000, seed=0, eps=0.02, links=RR_LINKS):
+    """The RR validation task (Sec. VII, Table II): joint box [q_lo, q_ub], a
+    task-space point obstacle, a unit impulse at q_goal with zero boundary
+    data, query q_start.  distance "ik": the collision set as N_col = 200
+    point obstacles (radius 0); "lipschitz": the planar-arm bound
+    d_tau / K."""
+    d = 2
+    s = _empty(d)
+    if distance == "ik":
+        P = rr_collision_points(links)
+        s.update(sph_c=P, sph_r=np.zeros(len(P)))
+    elif distance == "lipschitz":
+        s["arm"] = {"l": np.array(links, dtype=np.float64), "pts": np.array([RR_X_OBS], dtype=np.float64)}
+    else:
+        raise ValueError(distance)
+    s.update(d=d, goal_c=None, goal_r=None,
+             outer={"kind": "box", "lo": np.array(RR_Q_LO), "hi": np.array(RR_Q_HI)},
+             bdata=_bdata(0, d, g_goal=0.0, g_obs=0.0, g_outer=0.0),
+             source={"z": np.array(RR_Q_GOAL), "amp": 1.0, "c_imp": 1.0},
+             sigma=float(sigma), eps=float(eps), queries=np.array([RR_Q_START]),
+             n_walks=n_walks, seed=seed, s_ub=0.1, name=f"rr_{distance}_c{sigma:g}")
+    return s
+
+
 def plane_wave_k(d, sigma, seed=0):
     """A wave vector k with |k|^2 = sigma, direction drawn from the seed."""
     rng = np.random.default_rng(1000 + seed)
