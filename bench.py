@@ -326,6 +326,48 @@ def eval_env_sweep(B, torch, dims=(2, 3, 4, 5), ns=(10 ** 3, 10 ** 4, 10 ** 5, 1
     return out
 
 
+def rr_validation(B, torch, n_walks=100000, max_steps=300):
+    """The RR task of Sec. VII (Table II): gradient ascent from q_start to a
+    unit impulse at q_goal, 1e5 walks per gradient, s = min(0.1, d/2),
+    eps = 0.02, c = 0 and 5, with the IK-point distance (N_col = 200) and the
+    Lipschitz arm bound.  Link lengths and joint lower bounds are not in the
+    paper (unit links, joints spanning 2 pi), so its path lengths are context,
+    not a target."""
+    from paper_2406_01713_amd import scenes as S
+    out = {"n_walks": n_walks, "s_ub": 0.1, "eps": 0.02, "links": list(S.RR_LINKS),
+           "q_start": list(S.RR_Q_START), "q_goal": list(S.RR_Q_GOAL),
+           "paper_path_lengths": {"c=0": 4.5, "c=5": 3.8}, "runs": {}}
+    st = torch.cuda.current_stream()
+    for distance in ("ik", "lipschitz"):
+        for sigma in (0.0, 5.0):
+            s = S.scene_rr(distance, sigma=sigma, n_walks=n_walks)
+            x = torch.as_tensor(np.array([S.RR_Q_START]), dtype=torch.float32, device="cuda")
+            plan = B.Plan(B.Domain(s), x, n_walks, s["sigma"], s["eps"], s["s_ub"], s["seed"])
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            steps = 0
+            status = 0
+            while steps < max_steps:
+                plan.step(10)
+                steps += 10
+                r = plan.read()
+                status = int(r[4][0])
+                if status != 0:
+                    break
+            e1.record(st)
+            torch.cuda.synchronize()
+            u, g, path, stalls, sts, step = plan.read()
+            out["runs"][f"{distance}_c{sigma:g}"] = {
+                "path_length": float(path[0]), "arrived": int(sts[0]) == 1, "plan_steps": int(step[0]),
+                "stalls": int(stalls[0]), "ms_per_plan_step": e0.elapsed_time(e1) / max(int(step[0]), 1),
+                "end": [float(v) for v in x.cpu().numpy()[0]]}
+            del plan
+            log(f"RR {distance} c={sigma:g}: path {float(path[0]):.3f}, arrived {int(sts[0]) == 1}, "
+                f"{int(step[0])} steps")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -559,6 +601,11 @@ def main():
             log(f"planning to a point source: {out['planning_d7_point_source']['arrived']} / "
                 f"{out['planning_d7_point_source_near_goal']['arrived']} arrived "
                 f"({time.perf_counter() - t:.1f} s)")
+
+    if not args.no_plan:
+        t = time.perf_counter()
+        out["rr_validation"] = rr_validation(B, torch)
+        log(f"RR validation ({time.perf_counter() - t:.1f} s)")
 
     if not args.no_eval_env:
         t = time.perf_counter()

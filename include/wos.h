@@ -124,6 +124,22 @@ typedef struct {
     double b;            /* affine offset */
 } wos_bdata;
 
+/* Planar serial arm with revolute joints (Sec. V-B): the walk coordinates are
+ * the d joint angles, link i (length l_i) points along q_1 + ... + q_i in the
+ * task plane, and the base joint sits at the plane's origin.  Obstacle points
+ * in the task plane make the configurations that put a link on a point the
+ * arm's part of the boundary.  The walk uses the lower bound d_tau(q) / K of
+ * the joint-space distance to it: d_tau the planar distance between the
+ * points and the links (segments), K = sqrt(sum_n (l_n + ... + l_d)^2), which
+ * bounds how fast any point of the arm moves per unit of joint motion (the
+ * printed sum over the first n links agrees for equal links).  A walk
+ * absorbed there takes g_obstacle. */
+typedef struct {
+    const double* lengths;  /* host, d: link lengths >= 0, not all 0 */
+    int64_t n_points;       /* obstacle points in the task plane, >= 1 */
+    const double* points;   /* host, n_points x 2 */
+} wos_arm;
+
 /* Point source f = amplitude * delta_z (Sec. VI and VII: a unit impulse at the
  * goal point, with zero boundary data).  A walk step whose largest empty ball
  * holds z adds amplitude G_B(x_k, z), weighted by the step's screening
@@ -146,21 +162,22 @@ typedef struct {
 
 /*
  * wos_create_domain -- copy a domain description to the current device.
- * Omega = outer \ (goal ball U spheres U boxes) (Sec. V: the walk only needs
- * the distance to the boundary; here exact signed distances of the
- * components and their minimum).  goal may be NULL (no goal set); spheres
- * and boxes may be NULL (none).  The distance to the boundary is the minimum
- * of the components' signed distances; ties resolve to the goal, then spheres
- * by index, then boxes, then the outer boundary.  With 64 or more spheres
+ * Omega = outer \ (goal ball U spheres U boxes U arm collisions) (Sec. V:
+ * the walk only needs the distance to the boundary, or a lower bound of it;
+ * here exact signed distances of the components, the arm's Lipschitz bound,
+ * and their minimum).  goal may be NULL (no goal set); spheres, boxes and
+ * arm may be NULL (none).  Ties resolve to the goal, then spheres by index,
+ * then boxes, then the arm, then the outer boundary.  With 64 or more spheres
  * (boxes) the domain also keeps them grouped in clusters of 8 with bounding
  * spheres; the walk kernels skip a cluster that provably holds no nearer
  * obstacle, which changes the work done, never a distance or a walk.
  * source may be NULL (no volume source, the boundary-data problem).
  * Errors: WOS_EDIM, WOS_EINVAL (NULL out/outer/bdata, non-finite values,
- * negative radii, empty box, bad source, geom_d outside [0, d], boxes with
- * geom_d < d), WOS_ENOMEM, WOS_EHIP.
+ * negative radii, empty box, bad source, geom_d outside [0, d], boxes or an
+ * arm with geom_d < d, bad arm), WOS_ENOTSUP (an arm with affine or
+ * plane-wave data), WOS_ENOMEM, WOS_EHIP.
  */
-int wos_create_domain(int d, const wos_spheres* spheres, const wos_boxes* boxes,
+int wos_create_domain(int d, const wos_spheres* spheres, const wos_boxes* boxes, const wos_arm* arm,
                       const wos_ball* goal, const wos_outer* outer, const wos_bdata* bdata,
                       const wos_source* source, wos_domain** out);
 
@@ -326,7 +343,7 @@ int wos_varadhan(const void* u, const void* grad_u, int64_t n, int d, int stride
  * d values (cast to the compute type); q_index is the query's RNG index.
  * out_records (host double, n x (d + 7)): [u_hat, grad_hat[d], S, goal_w,
  * steps, status (0 absorbed, 1 degenerate, 2 truncated), class (0 goal,
- * 1 sphere, 2 box, 3 outer), d u_hat / d sigma].  Synchronous.
+ * 1 sphere, 2 box, 3 outer, 4 arm), d u_hat / d sigma].  Synchronous.
  */
 int wos_debug_walks(const wos_domain* dom, const double* query, uint32_t q_index, int64_t w0,
                     int64_t n, double sigma, double eps, uint64_t seed, const wos_options* opt,

@@ -60,6 +60,10 @@ class BData(C.Structure):
                 ("g_outer", C.c_double), ("a_or_k", C.POINTER(C.c_double)), ("b", C.c_double)]
 
 
+class Arm(C.Structure):
+    _fields_ = [("lengths", C.POINTER(C.c_double)), ("n_points", C.c_int64), ("points", C.POINTER(C.c_double))]
+
+
 class Source(C.Structure):
     _fields_ = [("z", C.POINTER(C.c_double)), ("amplitude", C.c_double), ("c_imp", C.c_double)]
 
@@ -75,8 +79,9 @@ def _load():
                           "(the estimator has no CPU fallback)")
     L = C.CDLL(LIB_PATH)
     vp, i64, u64, u32, dp = C.c_void_p, C.c_int64, C.c_uint64, C.c_uint32, C.POINTER(C.c_double)
-    L.wos_create_domain.argtypes = [C.c_int, C.POINTER(Spheres), C.POINTER(Boxes), C.POINTER(Ball),
-                                    C.POINTER(Outer), C.POINTER(BData), C.POINTER(Source), C.POINTER(vp)]
+    L.wos_create_domain.argtypes = [C.c_int, C.POINTER(Spheres), C.POINTER(Boxes), C.POINTER(Arm),
+                                    C.POINTER(Ball), C.POINTER(Outer), C.POINTER(BData), C.POINTER(Source),
+                                    C.POINTER(vp)]
     L.wos_destroy_domain.argtypes = [vp]
     L.wos_destroy_domain.restype = None
     L.wos_domain_dim.argtypes = [vp]
@@ -191,8 +196,14 @@ class Domain:
             z = arr(scene["source"]["z"], (d,))
             src = Source(_dp(z), float(scene["source"].get("amp", 1.0)),
                          float(scene["source"].get("c_imp", 1.0)))
+        arm = None
+        if scene.get("arm") is not None:
+            al = arr(scene["arm"]["l"], (d,))
+            ap = arr(scene["arm"]["pts"], (-1, 2))
+            arm = Arm(_dp(al), len(ap), _dp(ap))
         h = C.c_void_p()
-        check(lib.wos_create_domain(d, C.byref(sph), C.byref(box), C.byref(goal) if goal else None,
+        check(lib.wos_create_domain(d, C.byref(sph), C.byref(box), C.byref(arm) if arm else None,
+                                    C.byref(goal) if goal else None,
                                     C.byref(outer), C.byref(bd), C.byref(src) if src else None, C.byref(h)))
         self.handle = h
         self.n_obstacles = ns + nb

@@ -66,6 +66,11 @@ bool finite_all(const double* p, int64_t n)
 struct wos_domain {
     int d = 0;
     int geom_d = 0;  // obstacles and the outer boundary use the first geom_d coordinates
+    int64_t n_arm = 0;  // planar arm: task-plane obstacle points (0: no arm)
+    double arm_l[kMaxDim] = {0};
+    double arm_K = 0;
+    float* arm_f = nullptr;
+    double* arm_d = nullptr;
     int device = 0;
     int64_t n_sph = 0, n_box = 0;
     float* sph_f = nullptr;
@@ -160,6 +165,12 @@ int make_env(const wos_domain* D, double sigma, double eps, uint64_t seed, uint3
     p.d = D->d;
     p.geom_d = D->geom_d;
     p.pad_g = 0;
+    if (D->n_arm > 0) {
+        p.arm_pts = sizeof(T) == 4 ? (const T*)D->arm_f : (const T*)D->arm_d;
+        p.n_arm = (int32_t)D->n_arm;
+        for (int i = 0; i < kMaxDim; ++i) p.arm_l[i] = (T)D->arm_l[i];
+        p.arm_invK = (T)(1.0 / D->arm_K);
+    }
     p.has_goal = D->has_goal ? 1 : 0;
     p.outer_kind = D->outer_kind;
     p.mode = D->mode;
@@ -611,7 +622,8 @@ double unit_cost(const wos_domain* D, int64_t wps)
 {
     static const double steps[9] = {0, 0, 12, 25, 40, 55, 71, 85, 95};
     const int d = D->d;
-    const double per_step = (double)D->n_sph * (2 * d + 3) + (double)D->n_box * (5 * d + 4) + 150.0 * ((d + 3) / 4);
+    const double per_step = (double)D->n_sph * (2 * d + 3) + (double)D->n_box * (5 * d + 4) +
+                            (double)D->n_arm * d * 12 + 150.0 * ((d + 3) / 4);
     return per_step * steps[d] * (double)wps;
 }
 
@@ -760,8 +772,9 @@ extern "C" {
 
 const char* wos_last_error(void) { return g_err.c_str(); }
 
-int wos_create_domain(int d, const wos_spheres* spheres, const wos_boxes* boxes, const wos_ball* goal,
-                      const wos_outer* outer, const wos_bdata* bdata, const wos_source* source, wos_domain** out)
+int wos_create_domain(int d, const wos_spheres* spheres, const wos_boxes* boxes, const wos_arm* arm,
+                      const wos_ball* goal, const wos_outer* outer, const wos_bdata* bdata,
+                      const wos_source* source, wos_domain** out)
 {
     if (!out) return fail(WOS_EINVAL, "out is NULL");
     *out = nullptr;
@@ -779,6 +792,24 @@ int wos_create_domain(int d, const wos_spheres* spheres, const wos_boxes* boxes,
     const int gd = outer->geom_d == 0 ? d : outer->geom_d;
     if (gd < 1 || gd > d) return fail(WOS_EINVAL, "geom_d = %d outside [0, %d]", outer->geom_d, d);
     if (gd < d && nb > 0) return fail(WOS_EINVAL, "box obstacles need the full space (geom_d = d)");
+    double arm_K = 0.0;
+    if (arm) {
+        if (!arm->lengths || !arm->points || arm->n_points < 1 || arm->n_points > (int64_t)INT32_MAX)
+            return fail(WOS_EINVAL, "arm needs lengths and 1 <= n_points < 2^31 points");
+        if (!finite_all(arm->lengths, d) || !finite_all(arm->points, 2 * arm->n_points))
+            return fail(WOS_EINVAL, "non-finite arm lengths or points");
+        for (int n = 0; n < d; ++n) {
+            if (arm->lengths[n] < 0.0) return fail(WOS_EINVAL, "arm link lengths must be >= 0");
+            double reach = 0.0;  // joint n moves every point beyond it at most this fast
+            for (int i = n; i < d; ++i) reach += arm->lengths[i];
+            arm_K += reach * reach;
+        }
+        arm_K = std::sqrt(arm_K);
+        if (!(arm_K > 0.0)) return fail(WOS_EINVAL, "arm links are all of length 0");
+        if (gd < d) return fail(WOS_EINVAL, "an arm needs the full space (geom_d = d)");
+        if (bdata->mode != WOS_BDATA_CLASS)
+            return fail(WOS_ENOTSUP, "an arm bound names no boundary point: class boundary data only");
+    }
     // extruded geometry: sphere centres without their trailing coordinates
     std::vector<double> sc_ext;
     wos_spheres sph_ext;
@@ -840,6 +871,11 @@ int wos_create_domain(int d, const wos_spheres* spheres, const wos_boxes* boxes,
         delete D;
         return fail(WOS_EINVAL, "unknown outer kind %d", outer->kind);
     }
+    if (arm) {
+        D->n_arm = arm->n_points;
+        for (int i = 0; i < d; ++i) D->arm_l[i] = arm->lengths[i];
+        D->arm_K = arm_K;
+    }
     if (source) {
         D->has_src = true;
         for (int i = 0; i < d; ++i) D->src_z[i] = source->z[i];
@@ -873,6 +909,14 @@ int wos_create_domain(int d, const wos_spheres* spheres, const wos_boxes* boxes,
     if (e == hipSuccess) e = hipMemcpy(D->sph_d, sd.data(), sd.size() * sizeof(double), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(D->box_f, bf.data(), bf.size() * sizeof(float), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(D->box_d, bd.data(), bd.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess && D->n_arm > 0) {
+        const size_t na = 2 * (size_t)D->n_arm;
+        std::vector<float> af(arm->points, arm->points + na);
+        e = hipMalloc(&D->arm_f, na * sizeof(float));
+        if (e == hipSuccess) e = hipMalloc(&D->arm_d, na * sizeof(double));
+        if (e == hipSuccess) e = hipMemcpy(D->arm_f, af.data(), na * sizeof(float), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(D->arm_d, arm->points, na * sizeof(double), hipMemcpyHostToDevice);
+    }
     // clustered tables for large obstacle sets
     std::vector<int64_t> idx_s, idx_b;
     D->n_cl_sph = (int32_t)cluster_order(d, ns, ns ? spheres->centers : nullptr, idx_s);
@@ -931,6 +975,8 @@ void wos_destroy_domain(wos_domain* D)
     (void)hipFree(D->box_d);
     (void)hipFree(D->cl_f);
     (void)hipFree(D->cl_d);
+    (void)hipFree(D->arm_f);
+    (void)hipFree(D->arm_d);
     delete D;
 }
 
@@ -1367,7 +1413,7 @@ int wos_autotune(int d, int64_t M, int64_t Q, int64_t n_walks, const char* cache
     wos_outer ob{WOS_OUTER_BOX, lo.data(), hi.data(), nullptr, 0};
     wos_bdata bdv{WOS_BDATA_CLASS, 1.0, 0.0, 0.0, nullptr, 0.0};
     wos_domain* D = nullptr;
-    int rc = wos_create_domain(d, &sp, nullptr, &goal, &ob, &bdv, nullptr, &D);
+    int rc = wos_create_domain(d, &sp, nullptr, nullptr, &goal, &ob, &bdv, nullptr, &D);
     if (rc) return rc;
     std::vector<float> hq((size_t)Q * kBatchStride, 0.f);
     for (int64_t q = 0; q < Q; ++q)

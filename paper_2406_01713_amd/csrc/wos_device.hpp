@@ -65,6 +65,15 @@ struct Math<float> {
     static __device__ __forceinline__ float exp(float x) { return __expf(x); }
     static __device__ __forceinline__ float log(float x) { return __logf(x); }
     static __device__ __forceinline__ float pow(float x, float y) { return __expf(y * __logf(x)); }
+    // sin and cos of x radians: x in turns, reduced to [-1/2, 1/2], on the
+    // hardware sine and cosine (no wide-range reduction code)
+    static __device__ __forceinline__ void sincos(float x, float& s, float& c)
+    {
+        float t = x * 0.15915494309189535f;
+        t -= __builtin_rintf(t);
+        s = __builtin_amdgcn_sinf(t);
+        c = __builtin_amdgcn_cosf(t);
+    }
     // Box-Muller radius sqrt(-2 ln u) with ln u = ln 2 * log2 u
     static __device__ __forceinline__ float bm_radius(float u)
     {
@@ -96,6 +105,7 @@ struct Math<double> {
     static __device__ __forceinline__ double exp(double x) { return ::exp(x); }
     static __device__ __forceinline__ double log(double x) { return ::log(x); }
     static __device__ __forceinline__ double pow(double x, double y) { return ::pow(x, y); }
+    static __device__ __forceinline__ void sincos(double x, double& s, double& c) { ::sincos(x, &s, &c); }
     static __device__ __forceinline__ double bm_radius(double u) { return ::sqrt(-2.0 * ::log(u)); }
     static __device__ __forceinline__ void sincos_turns(double t, double& s, double& c)
     {
@@ -410,6 +420,36 @@ __device__ __forceinline__ float cluster_min_mfma(cptr<float> rows, const float*
     return best;
 }
 
+// Planar arm (Sec. V-B): the task-plane distance between the obstacle points
+// and the links at joint angles x (link i turns by x_0 + ... + x_i, base joint
+// at the origin), times 1 / K, a lower bound of the joint-space distance to
+// collision.
+template <typename T, int D>
+__device__ __forceinline__ T arm_dist(cenv<T> p, const T (&x)[D])
+{
+    cptr<T> pts = to_const(p->arm_pts);
+    const int n = p->n_arm;
+    T ax = 0, ay = 0, th = 0, best = Math<T>::inf();  // squared distance
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        th += x[i];
+        T sn, cs;
+        Math<T>::sincos(th, sn, cs);
+        const T sx = p->arm_l[i] * cs, sy = p->arm_l[i] * sn;
+        const T ss = Math<T>::fma(sx, sx, sy * sy);
+        const T inv = ss > T(0) ? T(1) / ss : T(0);
+        for (int j = 0; j < n; ++j) {
+            const T px = pts[2 * j] - ax, py = pts[2 * j + 1] - ay;
+            const T t = Math<T>::min(Math<T>::max(Math<T>::fma(px, sx, py * sy) * inv, T(0)), T(1));
+            const T ex = px - t * sx, ey = py - t * sy;
+            best = Math<T>::min(best, Math<T>::fma(ex, ex, ey * ey));
+        }
+        ax += sx;
+        ay += sy;
+    }
+    return Math<T>::sqrt(best) * p->arm_invK;
+}
+
 // Obstacle distances evaluated, summed over the live lanes of a wave: the
 // scans are wave-uniform, so every lane evaluates the same rows, and the
 // tally is one wave-level count for the work statistics.  Callers run the
@@ -444,6 +484,10 @@ __device__ __forceinline__ T distance(cenv<T> p, const T (&x)[D], int& cls, Work
     for (int i = 0; i < D; ++i) xg[i] = (i < p->geom_d) ? x[i] : T(0);
     const T dout = outer_dist<T, D>(fresh(p), xg);
     p = fresh(p);
+    // the arm bound (joint coordinates, never extruded) tightens the scans
+    const T da = p->n_arm ? arm_dist<T, D>(p, x) : Math<T>::inf();
+    const T dga = Math<T>::min(dg, Math<T>::min(da, dout));
+    p = fresh(p);
     T db;
     uint32_t nb, ns;
     if (p->n_cl_box) {
@@ -452,13 +496,13 @@ __device__ __forceinline__ T distance(cenv<T> p, const T (&x)[D], int& cls, Work
         if constexpr (sizeof(T) == 4) {
             if (p->use_mfma) {
                 db = cluster_min_mfma<D, true>(to_const(p->box_cl), fresh(p)->box_mf, fresh(p)->n_cl_box, xg,
-                                               Math<T>::min(dg, dout), live, nb);
+                                               dga, live, nb);
                 done = true;
             }
         }
         if (!done)
             db = cluster_min<T, D, true>(to_const(fresh(p)->box_cl), to_const(fresh(p)->box_bnd), fresh(p)->n_cl_box, xg,
-                                         Math<T>::min(dg, dout), live, nb);
+                                         dga, live, nb);
     } else {
         db = boxes_min<T, D>(to_const(p->box), fresh(p)->n_box, xg);
         nb = (uint32_t)fresh(p)->n_box;
@@ -471,13 +515,13 @@ __device__ __forceinline__ T distance(cenv<T> p, const T (&x)[D], int& cls, Work
         if constexpr (sizeof(T) == 4) {
             if (p->use_mfma) {
                 ds = cluster_min_mfma<D, false>(to_const(p->sph_cl), fresh(p)->sph_mf, fresh(p)->n_cl_sph, xg,
-                                                Math<T>::min(Math<T>::min(dg, dout), db), live, ns);
+                                                Math<T>::min(dga, db), live, ns);
                 done = true;
             }
         }
         if (!done)
             ds = cluster_min<T, D, false>(to_const(fresh(p)->sph_cl), to_const(fresh(p)->sph_bnd), fresh(p)->n_cl_sph,
-                                          xg, Math<T>::min(Math<T>::min(dg, dout), db), live, ns);
+                                          xg, Math<T>::min(dga, db), live, ns);
     } else {
         ds = spheres_min<T, D>(to_const(p->sph), fresh(p)->n_sph, xg);
         ns = (uint32_t)fresh(p)->n_sph;
@@ -485,9 +529,10 @@ __device__ __forceinline__ T distance(cenv<T> p, const T (&x)[D], int& cls, Work
     const uint64_t lanes = (uint64_t)__popcll(__ballot(live));
     wc.sph += lanes * ns;
     wc.box += lanes * nb;
-    const T bo = Math<T>::min(db, dout);
+    const T ao = Math<T>::min(da, dout);
+    const T bo = Math<T>::min(db, ao);
     const T rest = Math<T>::min(ds, bo);
-    cls = (dg <= rest) ? kGoal : (ds <= bo) ? kSphere : (db <= dout) ? kBox : kOuter;
+    cls = (dg <= rest) ? kGoal : (ds <= bo) ? kSphere : (db <= ao) ? kBox : (da <= dout) ? kArm : kOuter;
     return Math<T>::min(dg, rest);
 }
 
@@ -587,6 +632,11 @@ __device__ __forceinline__ void closest_point_in(cenv<T> p, const T (&x)[D], int
 template <typename T, int D>
 __device__ __forceinline__ void closest_point(cenv<T> p, const T (&x)[D], int cls, T (&xb)[D])
 {
+    if (cls == kArm) {  // the arm bound names no boundary point (class data only)
+#pragma unroll
+        for (int i = 0; i < D; ++i) xb[i] = x[i];
+        return;
+    }
     const int k = (cls == kGoal) ? D : p->geom_d;
     T xg[D];
 #pragma unroll

@@ -12,7 +12,7 @@ constexpr int kWave = 64;          // CDNA wavefront width
 constexpr uint32_t kDefaultMaxSteps = 1u << 16;
 constexpr int kBatchStats = 15;    // columns of a batched stats row
 
-enum Class : int32_t { kGoal = 0, kSphere = 1, kBox = 2, kOuter = 3 };
+enum Class : int32_t { kGoal = 0, kSphere = 1, kBox = 2, kOuter = 3, kArm = 4 };
 enum Status : int32_t { kAbsorbed = 0, kDegenerate = 1, kTruncated = 2 };
 
 // Row strides of the device obstacle tables (elements): a sphere row holds
@@ -64,6 +64,10 @@ struct EnvP {
     int32_t use_mfma, pad_mf;    // 1: cluster tests on the matrix cores (FP32 kernels)
     int32_t d, has_goal;
     int32_t geom_d, pad_g;     // obstacles and the outer boundary depend on x[0..geom_d) only
+    const T* arm_pts;          // planar arm: n_arm x 2 task-plane obstacle points
+    int32_t n_arm, pad_arm;    // 0: no arm
+    T arm_l[kMaxDim];          // link lengths, one per joint coordinate
+    T arm_invK;                // 1 / K, K the arm's Lipschitz constant
     int32_t outer_kind, mode;  // outer: 0 box, 1 ball; mode: 0 class, 1 affine, 2 plane
     int32_t nt_C, nt_C1;       // Horner terms of 0F1(;d/2;y) and 0F1(;d/2+1;y)
     uint32_t key0, key1;       // Philox key (seed)

@@ -54,12 +54,12 @@ def test_create_domain_rejects_bad_dimension(B):
     o, keep = _outer(B, 8)
     bd = _bdata(B)
     for d in (0, 1, 9, 100):
-        rc = B.lib.wos_create_domain(d, None, None, None, C.byref(o), C.byref(bd), None, C.byref(h))
+        rc = B.lib.wos_create_domain(d, None, None, None, None, C.byref(o), C.byref(bd), None, C.byref(h))
         assert rc == B.WOS_EDIM
         assert b"outside" in B.lib.wos_last_error()
-    assert B.lib.wos_create_domain(3, None, None, None, None, C.byref(bd), None, C.byref(h)) == B.WOS_EINVAL
-    assert B.lib.wos_create_domain(3, None, None, None, C.byref(o), None, None, C.byref(h)) == B.WOS_EINVAL
-    assert B.lib.wos_create_domain(3, None, None, None, C.byref(o), C.byref(bd), None, None) == B.WOS_EINVAL
+    assert B.lib.wos_create_domain(3, None, None, None, None, None, C.byref(bd), None, C.byref(h)) == B.WOS_EINVAL
+    assert B.lib.wos_create_domain(3, None, None, None, None, C.byref(o), None, None, C.byref(h)) == B.WOS_EINVAL
+    assert B.lib.wos_create_domain(3, None, None, None, None, C.byref(o), C.byref(bd), None, None) == B.WOS_EINVAL
 
 
 def test_create_domain_rejects_bad_obstacles(B):
@@ -70,19 +70,19 @@ def test_create_domain_rejects_bad_obstacles(B):
     c = np.zeros((1, d))
     r = np.array([-0.5])
     sp = B.Spheres(1, c.ctypes.data_as(C.POINTER(C.c_double)), r.ctypes.data_as(C.POINTER(C.c_double)))
-    assert B.lib.wos_create_domain(d, C.byref(sp), None, None, C.byref(o), C.byref(bd), None, C.byref(h)) == B.WOS_EINVAL
+    assert B.lib.wos_create_domain(d, C.byref(sp), None, None, None, C.byref(o), C.byref(bd), None, C.byref(h)) == B.WOS_EINVAL
     r2 = np.array([np.nan])
     sp2 = B.Spheres(1, c.ctypes.data_as(C.POINTER(C.c_double)), r2.ctypes.data_as(C.POINTER(C.c_double)))
-    assert B.lib.wos_create_domain(d, C.byref(sp2), None, None, C.byref(o), C.byref(bd), None, C.byref(h)) == B.WOS_EINVAL
+    assert B.lib.wos_create_domain(d, C.byref(sp2), None, None, None, C.byref(o), C.byref(bd), None, C.byref(h)) == B.WOS_EINVAL
     sp3 = B.Spheres(1, None, None)
-    assert B.lib.wos_create_domain(d, C.byref(sp3), None, None, C.byref(o), C.byref(bd), None, C.byref(h)) == B.WOS_EINVAL
+    assert B.lib.wos_create_domain(d, C.byref(sp3), None, None, None, C.byref(o), C.byref(bd), None, C.byref(h)) == B.WOS_EINVAL
     bad = B.BData(7, 1.0, 0.0, 0.0, None, 0.0)
-    assert B.lib.wos_create_domain(d, None, None, None, C.byref(o), C.byref(bad), None, C.byref(h)) == B.WOS_EINVAL
+    assert B.lib.wos_create_domain(d, None, None, None, None, C.byref(o), C.byref(bad), None, C.byref(h)) == B.WOS_EINVAL
     lo = np.array([1.0, -1.0])
     hi = np.array([-1.0, 1.0])
     ob = B.Outer(B.WOS_OUTER_BOX, lo.ctypes.data_as(C.POINTER(C.c_double)),
                  hi.ctypes.data_as(C.POINTER(C.c_double)), None, 0.0)
-    assert B.lib.wos_create_domain(d, None, None, None, C.byref(ob), C.byref(bd), None, C.byref(h)) == B.WOS_EINVAL
+    assert B.lib.wos_create_domain(d, None, None, None, None, C.byref(ob), C.byref(bd), None, C.byref(h)) == B.WOS_EINVAL
 
 
 def test_create_domain_rejects_bad_extrusion(B):
@@ -94,20 +94,53 @@ def test_create_domain_rejects_bad_extrusion(B):
     oc = np.zeros(d)
     for gd in (-1, 4, 9):
         ob = B.Outer(B.WOS_OUTER_BALL, None, None, oc.ctypes.data_as(C.POINTER(C.c_double)), 2.0, gd)
-        assert B.lib.wos_create_domain(d, None, None, None, C.byref(ob), C.byref(bd), None, C.byref(h)) == B.WOS_EINVAL
+        assert B.lib.wos_create_domain(d, None, None, None, None, C.byref(ob), C.byref(bd), None, C.byref(h)) == B.WOS_EINVAL
         assert b"geom_d" in B.lib.wos_last_error()
     ob = B.Outer(B.WOS_OUTER_BALL, None, None, oc.ctypes.data_as(C.POINTER(C.c_double)), 2.0, 2)
     bc = np.zeros((1, d))
     bh = np.full((1, d), 0.1)
     bx = B.Boxes(1, bc.ctypes.data_as(C.POINTER(C.c_double)), bh.ctypes.data_as(C.POINTER(C.c_double)))
-    assert B.lib.wos_create_domain(d, None, C.byref(bx), None, C.byref(ob), C.byref(bd), None, C.byref(h)) == B.WOS_EINVAL
+    assert B.lib.wos_create_domain(d, None, C.byref(bx), None, None, C.byref(ob), C.byref(bd), None, C.byref(h)) == B.WOS_EINVAL
     assert b"full space" in B.lib.wos_last_error()
     # an outer box whose bounds are only given for the leading coordinates
     lo = np.array([-1.0, -1.0, np.nan])
     hi = np.array([1.0, 1.0, np.nan])
     ob2 = B.Outer(B.WOS_OUTER_BOX, lo.ctypes.data_as(C.POINTER(C.c_double)),
                   hi.ctypes.data_as(C.POINTER(C.c_double)), None, 0.0, 3)
-    assert B.lib.wos_create_domain(d, None, None, None, C.byref(ob2), C.byref(bd), None, C.byref(h)) == B.WOS_EINVAL
+    assert B.lib.wos_create_domain(d, None, None, None, None, C.byref(ob2), C.byref(bd), None, C.byref(h)) == B.WOS_EINVAL
+
+
+def test_create_domain_rejects_bad_arm(B):
+    """Arm descriptions are checked before any device call: points, lengths,
+    extrusion, and boundary data that would need a boundary point."""
+    d = 2
+    h = C.c_void_p()
+    o, keep = _outer(B, d)
+    bd = _bdata(B)
+    pts = np.array([[0.0, 1.3]])
+    P = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))
+
+    def make(lengths, n=1, points=pts):
+        return B.Arm(P(lengths), n, P(points))
+
+    good = np.array([1.0, 1.0])
+    for arm in (make(good, 0), make(np.array([1.0, -0.5])), make(np.array([0.0, 0.0])),
+                make(good, 1, np.array([[np.nan, 1.0]])), make(np.array([np.inf, 1.0]))):
+        rc = B.lib.wos_create_domain(d, None, None, C.byref(arm), None, C.byref(o), C.byref(bd), None, C.byref(h))
+        assert rc == B.WOS_EINVAL, B.lib.wos_last_error()
+    nul = B.Arm(None, 1, P(pts))
+    assert B.lib.wos_create_domain(d, None, None, C.byref(nul), None, C.byref(o), C.byref(bd), None,
+                                   C.byref(h)) == B.WOS_EINVAL
+    a = np.array([0.1, 0.2])
+    aff = B.BData(1, 0.0, 0.0, 0.0, P(a), 0.0)
+    assert B.lib.wos_create_domain(d, None, None, C.byref(make(good)), None, C.byref(o), C.byref(aff), None,
+                                   C.byref(h)) == B.WOS_ENOTSUP
+    oc = np.zeros(3)
+    ob = B.Outer(B.WOS_OUTER_BALL, None, None, P(oc), 2.0, 2)
+    g3 = np.ones(3)
+    assert B.lib.wos_create_domain(3, None, None, C.byref(make(g3)), None, C.byref(ob), C.byref(bd), None,
+                                   C.byref(h)) == B.WOS_EINVAL
+    assert b"full space" in B.lib.wos_last_error()
 
 
 def test_calls_reject_null_handles(B):
@@ -149,7 +182,7 @@ def test_create_domain_rejects_bad_source(B):
                 B.Source(None, 1.0, 1.0),
                 B.Source(z0.ctypes.data_as(C.POINTER(C.c_double)), 1.0, -1.0),
                 B.Source(z0.ctypes.data_as(C.POINTER(C.c_double)), np.inf, 1.0)):
-        rc = B.lib.wos_create_domain(d, None, None, None, C.byref(o), C.byref(bd), C.byref(src), C.byref(h))
+        rc = B.lib.wos_create_domain(d, None, None, None, None, C.byref(o), C.byref(bd), C.byref(src), C.byref(h))
         assert rc == B.WOS_EINVAL
         assert b"source" in B.lib.wos_last_error()
 
