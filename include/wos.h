@@ -69,6 +69,9 @@ extern "C" {
                             same walks and results, more work: for testing */
 #define WOS_SCALAR_CULL 4u /* FP32: cluster tests on the vector ALUs instead of the
                               matrix cores; same walks and results */
+#define WOS_WAVE_SCAN 8u   /* FP32: every lane scans the members of every cluster
+                              some lane of its wave needs, instead of queuing the
+                              needed (walker, cluster) pairs; same walks */
 
 /* boundary-data modes */
 #define WOS_BDATA_CLASS 0  /* g_goal / g_obstacle / g_outer per component */

@@ -161,7 +161,7 @@ int make_env(const wos_domain* D, double sigma, double eps, uint64_t seed, uint3
     p.box_bnd = cl ? cl + D->off_box_bnd : nullptr;
     p.sph_mf = D->cl_f ? D->cl_f + D->off_sph_mf : nullptr;
     p.box_mf = D->cl_f ? D->cl_f + D->off_box_mf : nullptr;
-    p.use_mfma = (sizeof(T) == 4 && !(o.flags & WOS_SCALAR_CULL)) ? 1 : 0;
+    p.use_mfma = (sizeof(T) != 4 || (o.flags & WOS_SCALAR_CULL)) ? 0 : (o.flags & WOS_WAVE_SCAN) ? 1 : 2;
     p.d = D->d;
     p.geom_d = D->geom_d;
     p.pad_g = 0;
@@ -469,7 +469,8 @@ int read_opts(const wos_options* opt, wos_options& o)
 {
     o = wos_options{WOS_FP32, 0u, 0u, 0u};
     if (opt) o = *opt;
-    if (o.flags & ~(WOS_FP64 | WOS_FULL_SCAN | WOS_SCALAR_CULL)) return fail(WOS_EINVAL, "unknown flags 0x%x", o.flags);
+    if (o.flags & ~(WOS_FP64 | WOS_FULL_SCAN | WOS_SCALAR_CULL | WOS_WAVE_SCAN))
+        return fail(WOS_EINVAL, "unknown flags 0x%x", o.flags);
     if (o.reserved != 0) return fail(WOS_EINVAL, "wos_options.reserved must be 0");
     return WOS_OK;
 }

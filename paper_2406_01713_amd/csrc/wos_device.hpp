@@ -450,6 +450,124 @@ __device__ __forceinline__ T arm_dist(cenv<T> p, const T (&x)[D])
     return Math<T>::sqrt(best) * p->arm_invK;
 }
 
+// ------------------------------------------------------------------------
+// Pair-compacted member scan (FP32).  The matrix-core test gives, per tile,
+// one ballot per (row tile, register): bit j + 16 g of ballot (rt, r) says
+// walker 16 rt + 4 g + r may need cluster 16 t + j.  Instead of every lane
+// scanning the members of every cluster some lane needs, each needed
+// (walker, cluster) pair is queued in LDS and the wave evaluates pairs 64 at
+// a time, lane k taking pair k: it fetches the walker's position from that
+// walker's lane, scans the cluster's members with vector loads, and folds the
+// result into the walker's minimum with an LDS atomic min.  Every lane's
+// result is the minimum over the same member distances a scan of its needed
+// clusters computes, so R and every walk are unchanged.
+// ------------------------------------------------------------------------
+
+// Order-preserving map between FP32 values and uint32 (LDS atomic min of
+// signed distances): non-negative values set the sign bit, negative ones
+// flip every bit.
+__device__ __forceinline__ uint32_t ord_of(float f)
+{
+    const uint32_t u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float float_of_ord(uint32_t o)
+{
+    return __uint_as_float((o & 0x80000000u) ? (o & 0x7FFFFFFFu) : ~o);
+}
+
+// per-wave queue of (cluster << 6 | walker) entries and per-walker minima
+__shared__ uint32_t g_pair_queue[kMaxWavesPerBlock][kPairCap];
+__shared__ uint32_t g_pair_best[kMaxWavesPerBlock][kWave];
+
+// Evaluate queue entries [base, base + count), count <= 64, one per lane.
+// All lanes of the wave take part (the walker positions move by lane
+// shuffles).
+template <int D, bool BOX>
+__device__ __forceinline__ void pair_round(cptr<float> rows, int n_cl, const uint32_t* queue, int base, int count,
+                                           const float (&x)[D], uint32_t* best)
+{
+    constexpr int S = BOX ? box_stride(D) : sph_stride(D);
+    const int lane = threadIdx.x & (kWave - 1);
+    const bool act = lane < count;
+    const uint32_t e = act ? queue[base + lane] : 0u;
+    const int w = (int)(e & (kWave - 1));
+    int c = (int)(e >> 6);
+    c = c < n_cl ? c : n_cl - 1;  // an entry never points past the table
+    float xw[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) xw[i] = __shfl(x[i], w, kWave);
+    if (act) {
+        cptr<float> r = rows + (int64_t)c * (kCluster * S);
+        float m = Math<float>::inf();
+        // two members per iteration: the rows arrive in vector registers, so a
+        // full unroll would hold all eight clusters' members at once
+#pragma unroll 2
+        for (int j = 0; j < kCluster; ++j)
+            m = Math<float>::min(m, BOX ? box_dist<float, D>(xw, r + j * S) : sphere_dist<float, D>(xw, r + j * S));
+        atomicMin(&best[w], ord_of(m));
+    }
+}
+
+// Min over the members of the clusters each lane may need (thr as for
+// cluster_min), with the cluster test on the matrix cores and the members
+// scanned pair by pair.  Requires every lane of the wave to be active and
+// blocks of at most kMaxWavesPerBlock waves.  evals: member distances
+// evaluated by the wave.
+template <int D, bool BOX>
+__device__ __forceinline__ float cluster_min_pairs(cptr<float> rows, const float* __restrict__ mf, int n_cl,
+                                                   const float (&x)[D], float thr, bool live, uint64_t& evals)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wv = (int)(threadIdx.x / kWave);
+    uint32_t* queue = g_pair_queue[wv];
+    uint32_t* best = g_pair_best[wv];
+    best[lane] = ord_of(Math<float>::inf());
+    float A[3][4];
+    mfma_walker_operands<D>(x, thr, live, A);
+    const mf4* tab = reinterpret_cast<const mf4*>(mf) + lane;
+    const int n_tiles = (n_cl + kMfmaTile - 1) / kMfmaTile;
+    const uint32_t wl = 4u * (uint32_t)(lane >> 4);
+    int qn = 0;  // queued pairs (wave-uniform), < 64 between ballots
+    uint64_t pairs = 0;
+    for (int t = 0; t < n_tiles; ++t) {
+        const mf4 b = tab[t * kWave];
+        const uint32_t ctile = ((uint32_t)(t * kMfmaTile) + (uint32_t)(lane & (kMfmaTile - 1))) << 6;
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt) {
+            mf4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(A[0][rt], b[0], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(A[1][rt], b[1], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(A[2][rt], b[2], acc, 0, 0, 0);
+            uint64_t bks[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) bks[r] = __ballot(!(acc[r] > 0.0f));  // NaN never skips
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const uint64_t bk = bks[r];
+                if (bk) {  // wave-uniform
+                    if ((bk >> lane) & 1u) {
+                        const uint32_t pos = (uint32_t)qn + __builtin_amdgcn_mbcnt_hi(
+                                                                (uint32_t)(bk >> 32),
+                                                                __builtin_amdgcn_mbcnt_lo((uint32_t)bk, 0u));
+                        queue[pos] = ctile | (uint32_t)(16 * rt + r) | wl;
+                    }
+                    const int nk = __popcll(bk);
+                    qn += nk;
+                    pairs += (uint64_t)nk;
+                    if (qn >= kWave) {
+                        qn -= kWave;
+                        pair_round<D, BOX>(rows, n_cl, queue, qn, kWave, x, best);
+                    }
+                }
+            }
+        }
+    }
+    if (qn > 0) pair_round<D, BOX>(rows, n_cl, queue, 0, qn, x, best);
+    evals += pairs * kCluster;
+    return float_of_ord(best[lane]);
+}
+
 // Obstacle distances evaluated, summed over the live lanes of a wave: the
 // scans are wave-uniform, so every lane evaluates the same rows, and the
 // tally is one wave-level count for the work statistics.  Callers run the
@@ -489,12 +607,17 @@ __device__ __forceinline__ T distance(cenv<T> p, const T (&x)[D], int& cls, Work
     const T dga = Math<T>::min(dg, Math<T>::min(da, dout));
     p = fresh(p);
     T db;
-    uint32_t nb, ns;
+    uint32_t nb, ns;         // member distances per lane (wave-uniform scans)
+    uint64_t eb = 0, es = 0;  // member distances of the wave (pair-compacted scans)
     if (p->n_cl_box) {
         nb = 0;
         bool done = false;
         if constexpr (sizeof(T) == 4) {
-            if (p->use_mfma) {
+            if (p->use_mfma == 2) {
+                db = cluster_min_pairs<D, true>(to_const(p->box_cl), fresh(p)->box_mf, fresh(p)->n_cl_box, xg,
+                                                dga, live, eb);
+                done = true;
+            } else if (p->use_mfma) {
                 db = cluster_min_mfma<D, true>(to_const(p->box_cl), fresh(p)->box_mf, fresh(p)->n_cl_box, xg,
                                                dga, live, nb);
                 done = true;
@@ -513,7 +636,11 @@ __device__ __forceinline__ T distance(cenv<T> p, const T (&x)[D], int& cls, Work
         ns = 0;
         bool done = false;
         if constexpr (sizeof(T) == 4) {
-            if (p->use_mfma) {
+            if (p->use_mfma == 2) {
+                ds = cluster_min_pairs<D, false>(to_const(p->sph_cl), fresh(p)->sph_mf, fresh(p)->n_cl_sph, xg,
+                                                 Math<T>::min(dga, db), live, es);
+                done = true;
+            } else if (p->use_mfma) {
                 ds = cluster_min_mfma<D, false>(to_const(p->sph_cl), fresh(p)->sph_mf, fresh(p)->n_cl_sph, xg,
                                                 Math<T>::min(dga, db), live, ns);
                 done = true;
@@ -527,8 +654,8 @@ __device__ __forceinline__ T distance(cenv<T> p, const T (&x)[D], int& cls, Work
         ns = (uint32_t)fresh(p)->n_sph;
     }
     const uint64_t lanes = (uint64_t)__popcll(__ballot(live));
-    wc.sph += lanes * ns;
-    wc.box += lanes * nb;
+    wc.sph += lanes * ns + es;
+    wc.box += lanes * nb + eb;
     const T ao = Math<T>::min(da, dout);
     const T bo = Math<T>::min(db, ao);
     const T rest = Math<T>::min(ds, bo);

@@ -44,6 +44,13 @@ constexpr int kClusterMin = 64;
 // operand of three 16x16x4 products), the 4th float unused.  Padding
 // clusters of the last tile, and one spare tile after it, have feature
 // 9 = 1e30 (always skipped).
+// Pair-compacted member scan: (walker, cluster) pairs that the matrix-core
+// test keeps are queued per wave in LDS and evaluated 64 at a time, one pair
+// per lane.  The queue holds fewer than 64 pairs between rounds plus at most
+// one ballot's 64, so 128 entries never overflow.
+constexpr int kPairCap = 128;
+constexpr int kMaxWavesPerBlock = 4;  // every walk kernel runs <= 256 threads per block
+
 constexpr int kMfmaTile = 16;
 constexpr int kMfmaFeat = 12;
 
@@ -61,7 +68,8 @@ struct EnvP {
     const float* box_mf;
     int32_t n_sph, n_box;
     int32_t n_cl_sph, n_cl_box;  // 0: scan the caller-order table instead
-    int32_t use_mfma, pad_mf;    // 1: cluster tests on the matrix cores (FP32 kernels)
+    int32_t use_mfma, pad_mf;    // FP32 cluster tests: 0 vector ALUs, 1 matrix cores with a
+                                 // wave-uniform member scan, 2 matrix cores with pair compaction
     int32_t d, has_goal;
     int32_t geom_d, pad_g;     // obstacles and the outer boundary depend on x[0..geom_d) only
     const T* arm_pts;          // planar arm: n_arm x 2 task-plane obstacle points

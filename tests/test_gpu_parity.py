@@ -30,7 +30,7 @@ def dev(a, dtype):
 
 
 def gpu_estimate(B, scene, fp64=False, queries=None, n_walks=None, seed=None, env_id=0,
-                 max_steps=0, sigma=None, eps=None, full_scan=False, scalar_cull=False):
+                 max_steps=0, sigma=None, eps=None, full_scan=False, scalar_cull=False, wave_scan=False):
     import torch
     dt = torch.float64 if fp64 else torch.float32
     dom = B.Domain(scene)
@@ -42,7 +42,8 @@ def gpu_estimate(B, scene, fp64=False, queries=None, n_walks=None, seed=None, en
     B.wos_estimate(dom, q, scene["n_walks"] if n_walks is None else n_walks,
                    scene["sigma"] if sigma is None else sigma, scene["eps"] if eps is None else eps,
                    scene["seed"] if seed is None else seed, u, g, st,
-                   opt=B.options(fp64, env_id, max_steps, full_scan=full_scan, scalar_cull=scalar_cull))
+                   opt=B.options(fp64, env_id, max_steps, full_scan=full_scan, scalar_cull=scalar_cull,
+                                 wave_scan=wave_scan))
     torch.cuda.synchronize()
     return u.cpu().numpy().astype(np.float64), g.cpu().numpy().astype(np.float64), st.cpu().numpy()
 
@@ -254,7 +255,8 @@ def _ragged(n_envs=10, q_cap=24, n_walks=512):
     return envs
 
 
-def gpu_batch(B, envs, n_walks, seed, ubar=None, torch_dtype=None, full_scan=False, scalar_cull=False):
+def gpu_batch(B, envs, n_walks, seed, ubar=None, torch_dtype=None, full_scan=False, scalar_cull=False,
+              wave_scan=False):
     import torch
     doms = [B.Domain(e) for e in envs]
     Qs = [len(e["queries"]) for e in envs]
@@ -273,7 +275,8 @@ def gpu_batch(B, envs, n_walks, seed, ubar=None, torch_dtype=None, full_scan=Fal
                   out_dsigma=torch.empty(len(envs), dtype=torch.float64, device="cuda"),
                   out_dg=torch.empty(len(envs), dtype=torch.float64, device="cuda"))
     B.wos_estimate_batch(doms, q, off, [e["sigma"] for e in envs], [e["eps"] for e in envs], n_walks,
-                         seed, u, g, st, opt=B.options(full_scan=full_scan, scalar_cull=scalar_cull), **kw)
+                         seed, u, g, st, opt=B.options(full_scan=full_scan, scalar_cull=scalar_cull,
+                                                       wave_scan=wave_scan), **kw)
     torch.cuda.synchronize()
     out = {"u": u.cpu().numpy(), "g": g.cpu().numpy(), "st": st.cpu().numpy(), "off": off}
     if ubar is not None:
@@ -364,22 +367,38 @@ def test_culling_changes_no_result_batch(B):
 
 
 def test_matrix_core_cull_matches_vector_cull(B):
-    """The FP32 cluster test on the matrix cores and on the vector ALUs skip
-    different (always non-minimal) clusters; walks and outputs are identical."""
+    """The FP32 cluster test on the matrix cores (members scanned pair by
+    pair, or by every lane of the wave) and on the vector ALUs skip different
+    (always non-minimal) clusters; walks and outputs are identical, and the
+    pair-compacted scan evaluates the fewest member distances."""
     for s in _cull_scenes():
         a = gpu_estimate(B, s)
         b = gpu_estimate(B, s, scalar_cull=True)
-        for x, y in zip(a, b):
+        c = gpu_estimate(B, s, wave_scan=True)
+        for x, y, z in zip(a, b, c):
             assert np.array_equal(x, y), s["name"]
+            assert np.array_equal(x, z), s["name"]
+        dom = B.Domain(s)
+        for q in range(2):
+            ra = B.wos_debug_walks(dom, s["queries"][q], q, 0, 128, s["sigma"], s["eps"], s["seed"],
+                                   opt=B.options())
+            rb = B.wos_debug_walks(dom, s["queries"][q], q, 0, 128, s["sigma"], s["eps"], s["seed"],
+                                   opt=B.options(full_scan=True))
+            assert np.array_equal(ra, rb), (s["name"], q)
     envs = _ragged(n_envs=12, q_cap=16, n_walks=256)
     rng = np.random.default_rng(10)
     ubar = rng.normal(size=sum(len(e["queries"]) for e in envs)).astype(np.float32)
     a = gpu_batch(B, envs, 256, 5, ubar=ubar)
     b = gpu_batch(B, envs, 256, 5, ubar=ubar, scalar_cull=True)
+    c = gpu_batch(B, envs, 256, 5, ubar=ubar, wave_scan=True)
     for k in ("u", "g", "dx", "ds", "dg"):
         assert np.array_equal(a[k], b[k]), k
+        assert np.array_equal(a[k], c[k]), k
     assert np.array_equal(a["st"][:, :12], b["st"][:, :12])
-    print(f"member distances per walk, matrix vs vector cull: {a['st'][:, 12].sum():.4g} vs {b['st'][:, 12].sum():.4g}")
+    assert np.array_equal(a["st"][:, :12], c["st"][:, :12])
+    ma, mb, mc = a["st"][:, 12].sum(), b["st"][:, 12].sum(), c["st"][:, 12].sum()
+    print(f"member distances per walk, pairs / wave scan / vector cull: {ma:.4g} / {mc:.4g} / {mb:.4g}")
+    assert ma <= mc and ma <= mb
 
 
 def test_batch_vs_oracle(B, oracle):
