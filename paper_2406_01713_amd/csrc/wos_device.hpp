@@ -529,7 +529,7 @@ __device__ __forceinline__ float cluster_min_pairs(cptr<float> rows, const float
     const int n_tiles = (n_cl + kMfmaTile - 1) / kMfmaTile;
     const uint32_t wl = 4u * (uint32_t)(lane >> 4);
     int qn = 0;  // queued pairs (wave-uniform), < 64 between ballots
-    uint64_t pairs = 0;
+    uint32_t rounds = 0;
     for (int t = 0; t < n_tiles; ++t) {
         const mf4 b = tab[t * kWave];
         const uint32_t ctile = ((uint32_t)(t * kMfmaTile) + (uint32_t)(lane & (kMfmaTile - 1))) << 6;
@@ -539,24 +539,27 @@ __device__ __forceinline__ float cluster_min_pairs(cptr<float> rows, const float
             acc = __builtin_amdgcn_mfma_f32_16x16x4f32(A[0][rt], b[0], acc, 0, 0, 0);
             acc = __builtin_amdgcn_mfma_f32_16x16x4f32(A[1][rt], b[1], acc, 0, 0, 0);
             acc = __builtin_amdgcn_mfma_f32_16x16x4f32(A[2][rt], b[2], acc, 0, 0, 0);
+            bool need[4];
             uint64_t bks[4];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) bks[r] = __ballot(!(acc[r] > 0.0f));  // NaN never skips
+            for (int r = 0; r < 4; ++r) {
+                need[r] = !(acc[r] > 0.0f);  // NaN never skips
+                bks[r] = __ballot(need[r]);
+            }
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const uint64_t bk = bks[r];
                 if (bk) {  // wave-uniform
-                    if ((bk >> lane) & 1u) {
+                    if (need[r]) {
                         const uint32_t pos = (uint32_t)qn + __builtin_amdgcn_mbcnt_hi(
                                                                 (uint32_t)(bk >> 32),
                                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)bk, 0u));
                         queue[pos] = ctile | (uint32_t)(16 * rt + r) | wl;
                     }
-                    const int nk = __popcll(bk);
-                    qn += nk;
-                    pairs += (uint64_t)nk;
+                    qn += __popcll(bk);
                     if (qn >= kWave) {
                         qn -= kWave;
+                        ++rounds;
                         pair_round<D, BOX>(rows, n_cl, queue, qn, kWave, x, best);
                     }
                 }
@@ -564,7 +567,7 @@ __device__ __forceinline__ float cluster_min_pairs(cptr<float> rows, const float
         }
     }
     if (qn > 0) pair_round<D, BOX>(rows, n_cl, queue, 0, qn, x, best);
-    evals += pairs * kCluster;
+    evals += ((uint64_t)rounds * kWave + (uint64_t)qn) * kCluster;
     return float_of_ord(best[lane]);
 }
 
