@@ -389,7 +389,8 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one MI355X: the walk kernels run on a single GPU "
-              "(multi-GPU sharding is described in DESIGN.md, not run). Use --gpus 1.", file=sys.stderr)
+              "(walk ranges and queries would shard across GPUs with one all-reduce of partial sums; not run here). "
+              "Use --gpus 1.", file=sys.stderr)
         sys.exit(2)
     if args.only_batched:
         args.no_plain = args.no_cpu = args.no_plan = args.no_se = args.no_source = args.no_eval_env = True
