@@ -477,8 +477,8 @@ __device__ __forceinline__ float float_of_ord(uint32_t o)
 }
 
 // per-wave queue of (cluster << 6 | walker) entries and per-walker minima
-__shared__ uint32_t g_pair_queue[kMaxWavesPerBlock][kPairCap];
-__shared__ uint32_t g_pair_best[kMaxWavesPerBlock][kWave];
+static __shared__ uint32_t g_pair_queue[kMaxWavesPerBlock][kPairCap];
+static __shared__ uint32_t g_pair_best[kMaxWavesPerBlock][kWave];
 
 // Evaluate queue entries [base, base + count), count <= 64, one per lane.
 // All lanes of the wave take part (the walker positions move by lane

@@ -533,3 +533,50 @@ def test_d6_forward_full_size_sampled(B, oracle, fused):
         se_g = gw.std(axis=0, ddof=1) / math.sqrt(len(uw))
         assert abs(u[q] - uw.mean()) <= 4 * se_u + 1e-7
         assert np.all(np.abs(g[q] - gw.mean(0)) <= 4 * se_g + 1e-7)
+
+
+def test_d7_bench_launch_sampled(B, oracle):
+    """The d = 7 workload in the benchmark's launch (the 7-D segment queries
+    plus the 83 7-D environments of the ragged batch, one fused forward +
+    backward persistent launch, u_bar = 1), with plane-wave boundary data so
+    that every query has signal: sampled queries recomputed by the oracle
+    walk by walk on the same streams, within 4 SE (u, grad u, dx)."""
+    import torch
+    envs = [S.scene_c3()] + S.scene_c4(dims={7})
+    envs = [S.with_bdata(e, 2, ak=S.plane_wave_k(e["d"], e["sigma"], seed=i)) for i, e in enumerate(envs)]
+    seed = envs[0]["seed"]
+    Qs = [len(e["queries"]) for e in envs]
+    off = np.concatenate([[0], np.cumsum(Qs)]).astype(np.int64)
+    n = int(off[-1])
+    qp = np.zeros((n, 8), dtype=np.float32)
+    for e, s in enumerate(envs):
+        qp[off[e]:off[e + 1], :7] = s["queries"]
+    q = dev(qp, torch.float32)
+    u = torch.empty(n, device="cuda")
+    g = torch.empty(n, 8, device="cuda")
+    st = torch.empty(n, 15, dtype=torch.float64, device="cuda")
+    ubar = torch.ones(n, device="cuda")
+    dx = torch.empty(n, 8, device="cuda")
+    ds = torch.empty(len(envs), dtype=torch.float64, device="cuda")
+    dg = torch.empty(len(envs), dtype=torch.float64, device="cuda")
+    B.wos_estimate_batch([B.Domain(e) for e in envs], q, off, [e["sigma"] for e in envs],
+                         [e["eps"] for e in envs], np.array([e["n_walks"] for e in envs]), seed, u, g, st,
+                         ubar, dx, ds, dg)
+    torch.cuda.synchronize()
+    u, g, dx = u.cpu().numpy(), g.cpu().numpy(), dx.cpu().numpy()
+    heavy = max(range(1, len(envs)), key=lambda e: len(envs[e]["sph_r"]))
+    rng = np.random.default_rng(17)
+    picks = [(0, 5), (heavy, 0)] + [(e, int(rng.integers(Qs[e]))) for e in rng.choice(np.arange(1, len(envs)), 2)]
+    for e, ql in picks:
+        s = envs[e]
+        dom = oracle.Domain(s)
+        vals = [oracle.walk(s, s["queries"][ql], w, ql, env=e, dom=dom) for w in range(s["n_walks"])]
+        uw = np.array([v["u"] for v in vals])
+        gw = np.array([v["grad"] for v in vals])
+        se_u = uw.std(ddof=1) / math.sqrt(len(uw))
+        se_g = gw.std(axis=0, ddof=1) / math.sqrt(len(uw))
+        r = off[e] + ql
+        assert abs(u[r] - uw.mean()) <= 4 * se_u + 1e-6, (e, ql, u[r], uw.mean(), se_u)
+        assert np.all(np.abs(g[r, :7] - gw.mean(0)) <= 4 * se_g + 1e-6), (e, ql)
+        assert np.allclose(dx[r, :7], g[r, :7], rtol=1e-6, atol=1e-9), (e, ql)
+        assert np.all(g[r, 7:] == 0)
