@@ -368,6 +368,37 @@ def rr_validation(B, torch, n_walks=100000, max_steps=300):
     return out
 
 
+def eval_env_paths(B, torch, sigmas=(0.1, 1.0, 10.0), n_walks=100000, max_steps=600):
+    """Screening and path length in the evaluation environment (Sec. VI-A,
+    d = 2, k_r = 0.3, eps = 0.01): gradient ascent from x_start,1 = (-8, 0)
+    to the unit impulse at (8, 0) with 1e5 walks per gradient and
+    s = min(0.1, d/2), for c = 0.1, 1 and 10.  The FP32 planning loop cannot
+    represent the weights at c = 10 over this distance: every step multiplies
+    the weight by 1 / I_0(sqrt(c) R), so a walk that reaches the source from
+    16 units away carries a weight below FP32's range and the gradient
+    estimate is 0 (the run stalls)."""
+    from paper_2406_01713_amd import scenes as S
+    out = {"start": [-8.0, 0.0], "goal": [8.0, 0.0], "n_walks": n_walks, "s_ub": 0.1, "runs": {}}
+    for c in sigmas:
+        s = S.scene_eval_env(2, k_r=0.3, sigma=c, eps=1e-2)
+        x = torch.as_tensor(s["queries"][:1], dtype=torch.float32, device="cuda")
+        plan = B.Plan(B.Domain(s), x, n_walks, c, s["eps"], 0.1, s["seed"])
+        steps = 0
+        while steps < max_steps:
+            plan.step(20)
+            steps += 20
+            if int(plan.read()[4][0]) != 0:
+                break
+        u, g, path, stalls, sts, step = plan.read()
+        out["runs"][f"c={c:g}"] = {"path_length": float(path[0]), "arrived": int(sts[0]) == 1,
+                                   "plan_steps": int(step[0]), "stalls": int(stalls[0]),
+                                   "end": [float(v) for v in x.cpu().numpy()[0]]}
+        del plan
+        log(f"eval env path c={c:g}: length {float(path[0]):.2f}, arrived {int(sts[0]) == 1}, "
+            f"stalls {int(stalls[0])}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -606,7 +637,8 @@ def main():
     if not args.no_plan:
         t = time.perf_counter()
         out["rr_validation"] = rr_validation(B, torch)
-        log(f"RR validation ({time.perf_counter() - t:.1f} s)")
+        out["eval_env_paths"] = eval_env_paths(B, torch)
+        log(f"RR validation and evaluation-environment paths ({time.perf_counter() - t:.1f} s)")
 
     if not args.no_eval_env:
         t = time.perf_counter()

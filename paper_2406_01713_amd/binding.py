@@ -211,7 +211,7 @@ class Domain:
 
     def __del__(self):
         h = getattr(self, "handle", None)
-        if h is not None and h.value:
+        if h is not None and h.value and lib is not None:  # lib is None during interpreter exit
             lib.wos_destroy_domain(h)
             self.handle = None
 
@@ -351,6 +351,6 @@ class Plan:
 
     def __del__(self):
         h = getattr(self, "handle", None)
-        if h is not None and h.value:
+        if h is not None and h.value and lib is not None:  # lib is None during interpreter exit
             lib.wos_plan_destroy(h)
             self.handle = None
