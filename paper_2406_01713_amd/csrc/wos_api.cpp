@@ -162,6 +162,8 @@ int make_env(const wos_domain* D, double sigma, double eps, uint64_t seed, uint3
     p.sph_mf = D->cl_f ? D->cl_f + D->off_sph_mf : nullptr;
     p.box_mf = D->cl_f ? D->cl_f + D->off_box_mf : nullptr;
     p.use_mfma = (sizeof(T) != 4 || (o.flags & WOS_SCALAR_CULL)) ? 0 : (o.flags & WOS_WAVE_SCAN) ? 1 : 2;
+    // a pair-queue entry holds the cluster index in 26 bits
+    if (p.use_mfma == 2 && (D->n_cl_sph >= (1 << 26) || D->n_cl_box >= (1 << 26))) p.use_mfma = 1;
     p.d = D->d;
     p.geom_d = D->geom_d;
     p.pad_g = 0;

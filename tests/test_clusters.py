@@ -187,3 +187,110 @@ def test_debug_clusters_rejects_bad_input(B):
     assert B.lib.wos_debug_clusters(3, None, None, 0, None, None, None, None, None) == B.WOS_EINVAL
     with pytest.raises(B.WosError):
         B.wos_debug_clusters(3, np.zeros((70, 3)), -np.ones(70))
+
+
+def _mfma_features(x, thr, bc, br, d):
+    """Walker features (FP32, as the kernel forms them) and cluster features
+    (FP64 rounded once to FP32, as the host forms them) of the matrix-core
+    cluster test, m = 2^-12."""
+    m = np.float32(2.0 ** -12)
+    n = len(x)
+    a = np.zeros((n, 12), np.float32)
+    a[:, :d] = x
+    xx = np.zeros(n, np.float32)
+    for i in range(d):
+        xx = (x[:, i].astype(np.float64) * x[:, i] + xx).astype(np.float32)       # fma
+    mt2 = ((m * thr).astype(np.float32) * thr).astype(np.float32)
+    a[:, 8] = (xx.astype(np.float64) * np.float32(1 - m) - mt2).astype(np.float32)  # fma
+    a[:, 9] = 1.0
+    a[:, 10] = (thr * thr).astype(np.float32)
+    a[:, 11] = thr
+    md = 2.0 ** -12
+    b = np.zeros((len(bc), 12), np.float32)
+    cc = (bc.astype(np.float64) ** 2).sum(1)
+    rho = br.astype(np.float64)
+    b[:, :d] = (-2.0 * bc.astype(np.float64)).astype(np.float32)
+    b[:, 8] = 1.0
+    b[:, 9] = (cc * (1 - md) - rho * rho * (1 + md)).astype(np.float32)
+    b[:, 10] = -1.0
+    b[:, 11] = (-2.0 * rho).astype(np.float32)
+    return a, b
+
+
+def _dot32(a, b, order):
+    """FP32 dot products of every row of a with every row of b, three ways a
+    4-deep matrix step may round: a chain of fused multiply-adds in feature
+    order or reversed, or rounded products summed in pairs per step of 4."""
+    A = a.astype(np.float64)[:, None, :]
+    Bm = b.astype(np.float64)[None, :, :]
+    acc = np.zeros((a.shape[0], b.shape[0]), np.float32)
+    if order == "fma":
+        for k in range(12):
+            acc = (A[..., k] * Bm[..., k] + acc).astype(np.float32)
+    elif order == "reverse":
+        for k in reversed(range(12)):
+            acc = (A[..., k] * Bm[..., k] + acc).astype(np.float32)
+    else:
+        for s in range(3):
+            p = [(A[..., 4 * s + k] * Bm[..., 4 * s + k]).astype(np.float32) for k in range(4)]
+            s01 = (p[0] + p[1]).astype(np.float32)
+            s23 = (p[2] + p[3]).astype(np.float32)
+            acc = (acc + (s01 + s23).astype(np.float32)).astype(np.float32)
+    return acc
+
+
+def _far_tight_sets():
+    """Point obstacles (radius 0) packed near (7, 7, ...): large |x|^2 and
+    |C|^2 against small cluster radii, where the FP32 rounding of the expanded
+    dot product is largest relative to the cluster bound's own slack."""
+    out = []
+    for d, seed in ((3, 21), (7, 22)):
+        rng = np.random.default_rng(seed)
+        c = 7.0 + rng.normal(scale=0.15, size=(256, d))
+        s = S._empty(d)
+        s.update(d=d, sph_c=c, sph_r=np.zeros(256))
+        out.append((f"far_tight_d{d}", s))
+    return out
+
+
+@pytest.mark.parametrize("order", ["fma", "reverse", "pairs"])
+def test_matrix_core_cull_test_is_sound_in_fp32(B, order):
+    """Wherever the matrix-core test skips a cluster for a walker (feature
+    dot product > 0, computed in FP32 in any of three rounding orders), every
+    member's FP32 distance exceeds the walker's threshold: thresholds are put
+    at, just below and just above the exact bound, the hardest cases."""
+    rng = np.random.default_rng(11)
+    for name, s in _sets() + _far_tight_sets():
+        d = s["d"]
+        out = B.wos_debug_clusters(d, s["sph_c"], s["sph_r"], s["box_c"], s["box_h"])
+        for kind in ("sph", "box"):
+            order_, bnd = out[kind]
+            if len(order_) == 0:
+                continue
+            if kind == "sph":
+                c = np.asarray(s["sph_c"], np.float32)
+                r = np.asarray(s["sph_r"], np.float32)
+                rad = r.astype(np.float64)
+            else:
+                c = np.asarray(s["box_c"], np.float32)
+                h = np.asarray(s["box_h"], np.float32)
+                rad = np.sqrt((h.astype(np.float64) ** 2).sum(1))
+            x = _probe_points(rng, c.astype(np.float64), rad, d, 400).astype(np.float32)
+            bc = bnd[:, :-1].astype(np.float32)
+            br = bnd[:, -1].astype(np.float32)
+            exact_lb = np.linalg.norm(x.astype(np.float64)[:, None] - bc.astype(np.float64)[None], axis=2) \
+                - br.astype(np.float64)[None]
+            dist = _sphere_d32(x, c, r) if kind == "sph" else _box_d32(x, c, h)
+            member_min = np.stack([dist[:, order_[g * CL:(g + 1) * CL][order_[g * CL:(g + 1) * CL] >= 0]].min(1)
+                                   for g in range(len(bnd))], axis=1)
+            checked = 0
+            for rel in (-1e-3, -1e-5, 0.0, 1e-5, 1e-3):
+                g = rng.integers(0, len(bnd), len(x))
+                thr = np.maximum(exact_lb[np.arange(len(x)), g] * (1 + rel), 1e-6).astype(np.float32)
+                a, b = _mfma_features(x, thr, bc, br, d)
+                D = _dot32(a, b, order)
+                skip = D > 0
+                bad = skip & ~(member_min > thr[:, None])
+                assert not bad.any(), (name, kind, rel, np.argwhere(bad)[:3])
+                checked += skip.sum()
+            assert checked > 0
