@@ -140,6 +140,20 @@ int make_env(const wos_domain* D, double sigma, double eps, uint64_t seed, uint3
     const int nC1 = series_coeffs(0.5 * D->d + 1.0, y_max, tol, cC1);
     if (nC < 0 || nC1 < 0)
         return fail(WOS_ENOTSUP, "sigma R_max^2 / 4 = %g needs more than %d series terms", y_max, kMaxTerms);
+    // Horner runs on c_k 2^(m k) and y 2^-m: every step is the unscaled one
+    // times an exact power of two, so the value is the same bit for bit, and
+    // the scaled coefficients stay in T's normal range (unscaled, FP32's c_k
+    // leave it from k ~ 20, and at sigma R^2 / 4 ~ 200 the lost terms hold
+    // about 1e-3 of the sum).  m: the largest with 2^m <= y_max whose scaled
+    // coefficients stay below 2^120 (FP32) or 2^1000 (FP64).
+    const double c_lim = std::ldexp(1.0, sizeof(T) == 4 ? 120 : 1000);
+    int m = (y_max > 1.0) ? (int)std::floor(std::log2(y_max)) : 0;
+    for (; m > 0; --m) {
+        bool ok = true;
+        for (int k = 0; k < nC && ok; ++k) ok = std::ldexp(cC[k], m * k) <= c_lim;
+        for (int k = 0; k < nC1 && ok; ++k) ok = std::ldexp(cC1[k], m * k) <= c_lim;
+        if (ok) break;
+    }
     p.sph = nullptr;
     p.box = nullptr;
     if (sizeof(T) == 4) {
@@ -197,10 +211,10 @@ int make_env(const wos_domain* D, double sigma, double eps, uint64_t seed, uint3
     p.b = (T)D->b;
     p.sigma = (T)sigma;
     p.eps = (T)eps;
-    p.qsigma = (T)(0.25 * sigma);
+    p.qsigma = (T)std::ldexp(0.25 * sigma, -m);
     for (int i = 0; i < kMaxTerms; ++i) {
-        p.cC[i] = (T)(i < nC ? cC[i] : 0.0);
-        p.cC1[i] = (T)(i < nC1 ? cC1[i] : 0.0);
+        p.cC[i] = (T)(i < nC ? std::ldexp(cC[i], m * i) : 0.0);
+        p.cC1[i] = (T)(i < nC1 ? std::ldexp(cC1[i], m * i) : 0.0);
     }
     if (D->has_src) {
         // Green's-function constants (see ball_green): nu = d/2 - 1
@@ -761,7 +775,7 @@ int run_batch(const wos_domain* const* envs, int n_envs, const float* queries, c
                               (uint32_t)seed, (uint32_t)(seed >> 32), nullptr, counter, partials, st),
             "persistent walk kernel");
     WOS_HIP(launch_finalize_batch(bwd, d_benv, n_envs, partials, grad_u, out_u, out_grad, kBatchStride,
-                                  out_stats, out_dx, out_dsigma, out_dg, counter, st),
+                                  out_stats, out_dx, out_dsigma, out_dg, nullptr, counter, st),
             "batch finalize");
     return WOS_OK;
 }
@@ -1230,6 +1244,7 @@ struct wos_plan {
     float* grad = nullptr;
     float* ubar = nullptr;
     float* dx = nullptr;
+    float* dir = nullptr;
     double* dsig = nullptr;
     double* dg = nullptr;
     double* partials = nullptr;
@@ -1248,7 +1263,7 @@ static void plan_free(wos_plan* P)
     if (!P) return;
     if (P->exec) (void)hipGraphExecDestroy(P->exec);
     if (P->graph) (void)hipGraphDestroy(P->graph);
-    void* bufs[] = {P->u, P->grad, P->ubar, P->dx, P->dsig, P->dg, P->partials, P->path_len,
+    void* bufs[] = {P->u, P->grad, P->ubar, P->dx, P->dir, P->dsig, P->dg, P->partials, P->path_len,
                     P->stalls, P->status, P->step, P->counter, P->env, P->benv};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
@@ -1297,6 +1312,7 @@ int wos_plan_create(const wos_domain* D, float* x, int64_t n_starts, int64_t n_w
     if (e == hipSuccess) e = hipMalloc(&P->grad, S * kBatchStride * sizeof(float));
     if (e == hipSuccess) e = hipMalloc(&P->ubar, S * sizeof(float));
     if (e == hipSuccess) e = hipMalloc(&P->dx, S * kBatchStride * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc(&P->dir, S * kBatchStride * sizeof(float));
     if (e == hipSuccess) e = hipMalloc(&P->dsig, sizeof(double));
     if (e == hipSuccess) e = hipMalloc(&P->dg, sizeof(double));
     if (e == hipSuccess) e = hipMalloc(&P->partials, (size_t)std::max<int64_t>(L.total_units, 1) * nacc(kMaxDim) * sizeof(double));
@@ -1326,8 +1342,8 @@ int wos_plan_create(const wos_domain* D, float* x, int64_t n_starts, int64_t n_w
         hipError_t e1 = launch_persistent(true, D->has_src, L.grid, 256, P->env, P->benv, 1, x, L.total_units,
                                           P->henv.key0, P->henv.key1, P->step, P->counter, P->partials, st);
         hipError_t e2 = launch_finalize_batch(true, P->benv, 1, P->partials, P->ubar, P->u, P->grad,
-                                              kBatchStride, nullptr, P->dx, P->dsig, P->dg, P->counter, st);
-        hipError_t e3 = launch_plan_update(D->d, P->env, x, S, P->grad, kBatchStride, (float)s_ub, P->path_len,
+                                              kBatchStride, nullptr, P->dx, P->dsig, P->dg, P->dir, P->counter, st);
+        hipError_t e3 = launch_plan_update(D->d, P->env, x, S, P->dir, kBatchStride, (float)s_ub, P->path_len,
                                            P->stalls, P->status, P->step, st);
         e = hipStreamEndCapture(st, &P->graph);
         if (e == hipSuccess) e = (e1 != hipSuccess) ? e1 : (e2 != hipSuccess) ? e2 : e3;

@@ -915,6 +915,7 @@ struct Walker {
     T gs0;     // c_imp amp |grad G_B(x_0, z)| / |z - x_0| (the first ball holds z)
     uint32_t k;
     uint32_t w;
+    int32_t ex;  // W, W1, src, src1 and srcS hold their values times 2^-ex (FP32 only)
 };
 
 template <typename T>
@@ -928,6 +929,7 @@ struct WalkEnd {
     T srcS;     // point source: source part of d u_hat / d sigma
     uint32_t steps;
     int32_t status, cls;
+    int32_t ex;  // u, gs, goal_w, ubd and srcS hold their values times 2^-ex
 };
 
 template <typename T, int D, int DA>
@@ -947,7 +949,41 @@ __device__ __forceinline__ void walker_start(Walker<T, DA>& s, const T (&xq)[DA]
     s.gs0 = T(0);
     s.k = 0;
     s.w = w;
+    s.ex = 0;
 }
+
+// FP32 walks: the weight product of a long walk at a large screening
+// coefficient leaves the FP32 range (1/I_0(sqrt(sigma) R) per step in d = 2,
+// so a walk whose radii sum to 50 weighs under 2^-200 at sigma = 10).  Once W
+// drops below 2^-32 its binary exponent moves into s.ex and W, W1 and the
+// source sums are scaled by the same power of two, which is exact; the
+// accumulators apply 2^ex in FP64.  The rescale is skipped when it would lift
+// one of the other terms past 2^100: they then outweigh every later
+// contribution by more than FP32 resolves.  The path never depends on W.
+template <bool SRC, bool BWD, int DA>
+__device__ __forceinline__ void renormalize(Walker<float, DA>& s)
+{
+    if (s.W < 0x1p-32f) {
+        int e;
+        const float m = ::frexpf(s.W, &e);
+        float big = s.W1;
+        if (SRC) big = ::fmaxf(big, ::fmaxf(::fabsf(s.src), ::fabsf(s.src1)));
+        if (SRC && BWD) big = ::fmaxf(big, ::fabsf(s.srcS));
+        if (::ldexpf(big, -e) < 0x1p100f) {
+            s.W = m;
+            s.W1 = ::ldexpf(s.W1, -e);
+            if (SRC) {
+                s.src = ::ldexpf(s.src, -e);
+                s.src1 = ::ldexpf(s.src1, -e);
+            }
+            if (SRC && BWD) s.srcS = ::ldexpf(s.srcS, -e);
+            s.ex += e;
+        }
+    }
+}
+
+template <bool SRC, bool BWD, int DA>
+__device__ __forceinline__ void renormalize(Walker<double, DA>&) {}
 
 // Returns true when the walk ended (e is then filled in).  (key0, key1) is
 // the Philox key of the launch, q the query's index in its environment.  The
@@ -968,6 +1004,7 @@ __device__ __forceinline__ bool walker_step(cenv<T> p0, Walker<T, DA>& s, uint32
         e.steps = k + 1;
         e.cls = cls;
         e.status = first ? kDegenerate : kAbsorbed;
+        e.ex = s.ex;
         e.u = s.W * g;
         e.gs = first ? T(0) : s.gfac * s.W1 * g;
         e.S = s.S;
@@ -985,6 +1022,7 @@ __device__ __forceinline__ bool walker_step(cenv<T> p0, Walker<T, DA>& s, uint32
         e.steps = k + 1;
         e.cls = cls;
         e.status = kTruncated;
+        e.ex = 0;
         e.u = T(0);
         e.gs = T(0);
         e.S = T(0);
@@ -1017,6 +1055,7 @@ __device__ __forceinline__ bool walker_step(cenv<T> p0, Walker<T, DA>& s, uint32
     p = fresh(p0);
     s.W *= C;
     s.W1 *= (k > 0) ? C : T(1);
+    renormalize<SRC, BWD>(s);
     if (BWD) {
         const T p1 = horner<T>(p->cC1, p->nt_C1, y);
         s.S = Math<T>::fma(T(-0.5 / D) * R2 * p1, C, s.S);

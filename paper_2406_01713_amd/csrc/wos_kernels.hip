@@ -49,22 +49,32 @@ __device__ __forceinline__ void wave_store(double (&a)[N], double* out)
     }
 }
 
-// One-point gradient of a finished walk: gs v0, plus gs0 (z - x_0) when a
-// point source lies in the first ball.
-template <typename T, int D, int DA, bool SRC>
-__device__ __forceinline__ T walk_grad(const WalkEnd<T>& e, const T (&v0)[DA], cenv<T> p, const T* xq, int i)
+// 2^ex: the factor between a finished walk's stored weighted terms and their
+// values (the FP32 walk keeps the weight's exponent apart; FP64 does not).
+template <typename T>
+__device__ __forceinline__ double walk_scale(const WalkEnd<T>& e)
 {
-    T g = e.gs * v0[i];
-    if (SRC) g = Math<T>::fma(e.gs0, p->src_z[i] - xq[i], g);
+    if (sizeof(T) == 8) return 1.0;
+    return ::ldexp(1.0, e.ex);
+}
+
+// One-point gradient of a finished walk: gs v0, plus gs0 (z - x_0) when a
+// point source lies in the first ball (gs0 carries no weight, so no scale).
+template <typename T, int D, int DA, bool SRC>
+__device__ __forceinline__ double walk_grad(const WalkEnd<T>& e, const T (&v0)[DA], cenv<T> p, const T* xq, int i,
+                                            double sc)
+{
+    const double g = (double)(e.gs * v0[i]) * sc;
+    if (SRC) return g + (double)(e.gs0 * (p->src_z[i] - xq[i]));
     return g;
 }
 
 // d u_hat / d sigma of a finished walk: (W g) S, plus the source part.
 template <typename T, bool SRC>
-__device__ __forceinline__ double walk_dsigma(const WalkEnd<T>& e)
+__device__ __forceinline__ double walk_dsigma(const WalkEnd<T>& e, double sc)
 {
-    if (SRC) return (double)e.ubd * (double)e.S + (double)e.srcS;
-    return (double)e.u * (double)e.S;
+    if (SRC) return ((double)e.ubd * (double)e.S + (double)e.srcS) * sc;
+    return (double)e.u * (double)e.S * sc;
 }
 
 // Contribution of one finished walk to an accumulator row laid out for DA
@@ -73,20 +83,21 @@ template <typename T, int D, int DA, bool SRC>
 __device__ __forceinline__ void accumulate(double (&a)[nacc(DA)], const WalkEnd<T>& e, const T (&v0)[DA],
                                            cenv<T> p, const T* xq)
 {
-    const double u = (double)e.u;
+    const double sc = walk_scale(e);
+    const double u = (double)e.u * sc;
     a[0] += u;
     a[1] += u * u;
 #pragma unroll
     for (int i = 0; i < D; ++i) {
-        const double g = (double)walk_grad<T, D, DA, SRC>(e, v0, p, xq, i);
+        const double g = walk_grad<T, D, DA, SRC>(e, v0, p, xq, i, sc);
         a[2 + i] += g;
         a[2 + DA + i] += g * g;
     }
     a[2 + 2 * DA] += (double)e.steps;
     a[3 + 2 * DA] += (e.status == kTruncated) ? 1.0 : 0.0;
     a[4 + 2 * DA] += (e.status == kDegenerate) ? 1.0 : 0.0;
-    a[5 + 2 * DA] += walk_dsigma<T, SRC>(e);
-    a[6 + 2 * DA] += (double)e.goal_w;
+    a[5 + 2 * DA] += walk_dsigma<T, SRC>(e, sc);
+    a[6 + 2 * DA] += (double)e.goal_w * sc;
 }
 
 // The wave's work tally goes into lane 0's accumulators before the wave sum.
@@ -128,6 +139,7 @@ plain_kernel(const EnvP<T>* penv, const T* __restrict__ queries, int64_t n_units
     walker_start<T, D, D>(s, xq, (uint32_t)(w_base + wi));
     WalkEnd<T> e;
     e.u = e.gs = e.S = e.goal_w = T(0);
+    e.ex = 0;
     e.steps = 0;
     e.status = kTruncated;
     e.cls = kOuter;
@@ -153,15 +165,16 @@ plain_kernel(const EnvP<T>* penv, const T* __restrict__ queries, int64_t n_units
 
     if (records != nullptr && active) {
         double* r = records + wi * (D + 7);
-        r[0] = (double)e.u;
+        const double sc = walk_scale(e);
+        r[0] = (double)e.u * sc;
 #pragma unroll
-        for (int i = 0; i < D; ++i) r[1 + i] = (double)walk_grad<T, D, D, SRC>(e, s.v0, p, xq, i);
+        for (int i = 0; i < D; ++i) r[1 + i] = walk_grad<T, D, D, SRC>(e, s.v0, p, xq, i, sc);
         r[D + 1] = (double)e.S;
-        r[D + 2] = (double)e.goal_w;
+        r[D + 2] = (double)e.goal_w * sc;
         r[D + 3] = (double)e.steps;
         r[D + 4] = (double)e.status;
         r[D + 5] = (double)e.cls;
-        r[D + 6] = walk_dsigma<T, SRC>(e);
+        r[D + 6] = walk_dsigma<T, SRC>(e, sc);
     }
 }
 
@@ -341,21 +354,22 @@ __device__ __forceinline__ void run_unit(cenv<float> p, CBatch& be, int64_t loca
         fin = fin && active;
         {
             if (fin) {
-                const double u = (double)e.u;
+                const double sc = walk_scale(e);
+                const double u = (double)e.u * sc;
                 a[0] += u;
                 a[1] += u * u;
                 a[2] += (double)e.steps;
                 a[3] += (e.status == kTruncated) ? 1.0 : 0.0;
                 a[4] += (e.status == kDegenerate) ? 1.0 : 0.0;
-                a[5] += walk_dsigma<float, SRC>(e);
-                a[6] += (double)e.goal_w;
+                a[5] += walk_dsigma<float, SRC>(e, sc);
+                a[6] += (double)e.goal_w * sc;
                 // static indices (unrolled, guarded by d) keep the walker in
                 // registers; a runtime loop bound would index it dynamically
                 // and move it to scratch memory
 #pragma unroll
                 for (int i = 0; i < kMaxDim; ++i) {
                     if (i < d) {
-                        const double gi = (double)walk_grad<float, kMaxDim, kMaxDim, SRC>(e, s.v0, p, xq, i);
+                        const double gi = walk_grad<float, kMaxDim, kMaxDim, SRC>(e, s.v0, p, xq, i, sc);
                         g[i * kWave] += gi;
                         g[(kMaxDim + i) * kWave] += gi * gi;
                     }
@@ -435,7 +449,7 @@ finalize_batch(const BatchEnv* __restrict__ benv, const double* __restrict__ par
                const float* __restrict__ ubar, float* __restrict__ out_u,
                float* __restrict__ out_grad, int grad_stride, double* __restrict__ out_stats,
                float* __restrict__ out_dx, double* __restrict__ out_dsigma,
-               double* __restrict__ out_dg, unsigned* counter)
+               double* __restrict__ out_dg, float* __restrict__ out_dir, unsigned* counter)
 {
     __shared__ double s0[kBlock], s1[kBlock];
     const BatchEnv be = benv[blockIdx.x];
@@ -454,6 +468,15 @@ finalize_batch(const BatchEnv* __restrict__ benv, const double* __restrict__ par
         constexpr int M = kMaxDim;
         if (out_grad)
             for (int i = 0; i < M; ++i) out_grad[qg * grad_stride + i] = (i < d) ? (float)(a[2 + i] / n) : 0.0f;
+        if (out_dir) {  // unit direction from the FP64 sums, scaled by the largest entry first
+            double m = 0.0, g2 = 0.0;
+            for (int i = 0; i < d; ++i) m = ::fmax(m, ::fabs(a[2 + i]));
+            if (m > 0.0)
+                for (int i = 0; i < d; ++i) g2 += (a[2 + i] / m) * (a[2 + i] / m);
+            const double r = (g2 > 0.0) ? 1.0 / ::sqrt(g2) : 0.0;
+            for (int i = 0; i < M; ++i)
+                out_dir[qg * grad_stride + i] = (i < d && m > 0.0) ? (float)((a[2 + i] / m) * r) : 0.0f;
+        }
         if (out_stats) {
             double* st = out_stats + qg * kBatchStats;
             st[0] = se_of(a[0], a[1], n);
@@ -497,7 +520,7 @@ finalize_batch(const BatchEnv* __restrict__ benv, const double* __restrict__ par
 // ------------------------------------------------------------------------
 template <int D>
 __global__ void __launch_bounds__(kBlock)
-plan_update(const EnvP<float>* penv, float* __restrict__ x, int64_t n, const float* __restrict__ grad,
+plan_update(const EnvP<float>* penv, float* __restrict__ x, int64_t n, const float* __restrict__ dir,
             int grad_stride, float s_ub, double* __restrict__ path_len, int32_t* __restrict__ stalls,
             int32_t* __restrict__ status, uint64_t* step)
 {
@@ -529,7 +552,7 @@ plan_update(const EnvP<float>* penv, float* __restrict__ x, int64_t n, const flo
             float g2 = 0.0f;
 #pragma unroll
             for (int i = 0; i < D; ++i) {
-                g[i] = grad[s * grad_stride + i];
+                g[i] = dir[s * grad_stride + i];
                 g2 = Math<float>::fma(g[i], g[i], g2);
             }
             if (g2 == 0.0f) {
@@ -728,26 +751,26 @@ int persistent_resident_blocks(bool bwd, bool src, int block)
 hipError_t launch_finalize_batch(bool bwd, const BatchEnv* benv, int n_benv, const double* partials,
                                  const float* ubar, float* out_u, float* out_grad,
                                  int grad_stride, double* out_stats, float* out_dx, double* out_dsigma,
-                                 double* out_dg, unsigned* counter, hipStream_t st)
+                                 double* out_dg, float* out_dir, unsigned* counter, hipStream_t st)
 {
     if (n_benv == 0) return hipSuccess;
     if (bwd)
-        hipLaunchKernelGGL(finalize_batch<true>, dim3(n_benv), dim3(kBlock), 0, st, benv, partials,
-                           ubar, out_u, out_grad, grad_stride, out_stats, out_dx, out_dsigma, out_dg, counter);
+        hipLaunchKernelGGL(finalize_batch<true>, dim3(n_benv), dim3(kBlock), 0, st, benv, partials, ubar, out_u,
+                           out_grad, grad_stride, out_stats, out_dx, out_dsigma, out_dg, out_dir, counter);
     else
-        hipLaunchKernelGGL(finalize_batch<false>, dim3(n_benv), dim3(kBlock), 0, st, benv, partials,
-                           ubar, out_u, out_grad, grad_stride, out_stats, out_dx, out_dsigma, out_dg, counter);
+        hipLaunchKernelGGL(finalize_batch<false>, dim3(n_benv), dim3(kBlock), 0, st, benv, partials, ubar, out_u,
+                           out_grad, grad_stride, out_stats, out_dx, out_dsigma, out_dg, out_dir, counter);
     return hipGetLastError();
 }
 
-hipError_t launch_plan_update(int d, const EnvP<float>* p, float* x, int64_t n, const float* grad,
+hipError_t launch_plan_update(int d, const EnvP<float>* p, float* x, int64_t n, const float* dir,
                               int grad_stride, float s_ub, double* path_len, int32_t* stalls,
                               int32_t* status, uint64_t* step, hipStream_t st)
 {
     const unsigned grid = n > 0 ? blocks_for(n, kBlock) : 1u;
 #define WOS_PLAN_CASE(DD)                                                                              \
     case DD:                                                                                           \
-        hipLaunchKernelGGL(plan_update<DD>, dim3(grid), dim3(kBlock), 0, st, p, x, n, grad, grad_stride, \
+        hipLaunchKernelGGL(plan_update<DD>, dim3(grid), dim3(kBlock), 0, st, p, x, n, dir, grad_stride,  \
                            s_ub, path_len, stalls, status, step);                                      \
         break;
     switch (d) {

@@ -41,14 +41,17 @@ hipError_t launch_persistent(bool bwd, bool src, int grid, int block, const EnvP
 int persistent_resident_blocks(bool bwd, bool src, int block);
 
 // Outputs of a batched launch; one block per env; also resets *counter.
+// out_dir (optional, rows like out_grad) receives grad / |grad| formed from
+// the FP64 sums, so it exists where the mean gradient is below FP32 range.
 hipError_t launch_finalize_batch(bool bwd, const BatchEnv* benv, int n_benv,
                                  const double* partials, const float* ubar,
                                  float* out_u, float* out_grad, int grad_stride,
                                  double* out_stats, float* out_dx, double* out_dsigma,
-                                 double* out_dg, unsigned* counter, hipStream_t st);
+                                 double* out_dg, float* out_dir, unsigned* counter, hipStream_t st);
 
-// One planning update: x += min(s_ub, R/2) grad / |grad|; bumps *step.
-hipError_t launch_plan_update(int d, const EnvP<float>* p, float* x, int64_t n, const float* grad,
+// One planning update: x += min(s_ub, R/2) dir, dir the unit gradient
+// direction (a zero row counts a stall); bumps *step.
+hipError_t launch_plan_update(int d, const EnvP<float>* p, float* x, int64_t n, const float* dir,
                               int grad_stride, float s_ub, double* path_len, int32_t* stalls,
                               int32_t* status, uint64_t* step, hipStream_t st);
 

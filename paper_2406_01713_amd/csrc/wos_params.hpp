@@ -87,9 +87,9 @@ struct EnvP {
     T orad;
     T g_goal, g_obs, g_outer, b;
     T ak[kMaxDim];
-    T sigma, eps, qsigma;      // qsigma = sigma / 4
-    T cC[kMaxTerms];           // c_k = 1 / ((d/2)_k k!)
-    T cC1[kMaxTerms];          // c_k = 1 / ((d/2 + 1)_k k!)
+    T sigma, eps, qsigma;      // qsigma = 2^-m sigma / 4 (m: the series scale)
+    T cC[kMaxTerms];           // 2^(m k) c_k, c_k = 1 / ((d/2)_k k!)
+    T cC1[kMaxTerms];          // 2^(m k) c_k, c_k = 1 / ((d/2 + 1)_k k!)
     // point source amp delta_z (has_src 0: none)
     int32_t has_src, pad_src;
     T src_z[kMaxDim];

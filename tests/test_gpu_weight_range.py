@@ -1,0 +1,119 @@
+"""FP32 walks whose weight product leaves the FP32 range (the per-step weight
+C(R) = 1 / 0F1(; d/2; sigma R^2 / 4) of Sec. IV-A at a large screening
+coefficient, in the evaluation environment of Sec. VI): per-walk estimates
+below 2^-126 agree with the FP64 oracle to a relative tolerance on identical
+Philox streams, the planner's step direction exists where the mean gradient
+is below the FP32 range and follows the oracle's step, and the c = 10 path
+from x_start,1 reaches the source (Sec. VI-A)."""
+import numpy as np
+import pytest
+
+from paper_2406_01713_amd import scenes as S
+from tests.test_gpu_parity import dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2406_01713_amd import binding
+    return binding
+
+
+def rel_bound(sigma, k):
+    """FP32 against FP64 on the same walk (same number of steps k): the FP32
+    position drifts from the FP64 one by about sqrt(i) ulp(8) = sqrt(i)
+    2^-20 after i steps (|x| < 16 here), every radius inherits that drift,
+    and ln W changes by sqrt(sigma) times the summed radius change, about
+    sqrt(sigma) (2/3) k^1.5 2^-20; twice that, and at least 1e-4."""
+    return max(1e-4, 2.0 * np.sqrt(sigma) * (2.0 / 3.0) * k ** 1.5 * 2.0 ** -20)
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_tiny_weights_match_the_oracle(B, oracle, d):
+    """sigma = 100: a quarter of the walks that reach the source carry a
+    weight below 2^-126; FP32 walks keep them, nonzero and within the drift
+    bound of the FP64 walk."""
+    q = np.zeros((3, d))
+    q[:, :2] = [[2.0, 0.5], [4.0, 2.0], [5.0, 3.5]]
+    s = S.scene_eval_env(d, k_r=0.3, sigma=100.0, eps=1e-2, queries=q, n_walks=256, seed=0)
+    dom = B.Domain(s)
+    odom = oracle.Domain(s)
+    n = s["n_walks"]
+    same = tiny = 0
+    worst = []
+    for qi, x in enumerate(q):
+        rec = B.wos_debug_walks(dom, x, qi, 0, n, s["sigma"], s["eps"], s["seed"], B.options(False))
+        for w in range(n):
+            r = oracle.walk(s, x, w, qi, dom=odom)
+            if int(rec[w, d + 3]) != r["steps"]:
+                continue
+            same += 1
+            assert int(rec[w, d + 4]) == r["status"]
+            if r["u"] == 0.0:
+                assert rec[w, 0] == 0.0 and np.all(rec[w, 1:1 + d] == 0.0), (qi, w)
+                continue
+            tiny += r["u"] < 2.0 ** -126
+            tol = rel_bound(s["sigma"], r["steps"])
+            gs = np.abs(r["grad"]).max()
+            eu = abs(rec[w, 0] - r["u"]) / r["u"]
+            eg = np.abs(rec[w, 1:1 + d] - r["grad"]).max() / gs
+            worst.append((max(eu, eg) / tol, eu, eg, r["steps"], r["u"], qi, w))
+    worst.sort(reverse=True)
+    for t in worst[:4]:
+        print("error / bound %.3f: rel u %.2e, rel grad %.2e, steps %d, u %.3e (query %d, walk %d)" % t)
+    assert worst and worst[0][0] <= 1.0, worst[:4]
+    assert same >= 0.8 * n * len(q), same
+    assert tiny >= 8, tiny
+
+
+def test_plan_direction_below_fp32_range(B, oracle):
+    """c = 10 from x_start,1 = (-8, 0): every walk that reaches the source
+    weighs below 2^-126 and the mean gradient is near 2^-160, yet the FP32
+    planning graph steps as the FP64 oracle does (two steps, 1e5 walks)."""
+    import torch
+    s = S.scene_eval_env(2, k_r=0.3, sigma=10.0, eps=1e-2, n_walks=100000, seed=0)
+    s["s_ub"] = 0.1
+    x0 = np.array([[-8.0, 0.0]])
+    x = dev(x0, torch.float32)
+    plan = B.Plan(B.Domain(s), x, s["n_walks"], s["sigma"], s["eps"], s["s_ub"], s["seed"])
+    xo = x0.copy()
+    path = np.zeros(1)
+    stalls = np.zeros(1, dtype=np.int32)
+    status = np.zeros(1, dtype=np.int32)
+    for t in range(2):
+        plan.step(1)
+        u, g, gpath, gstalls, sts, step = plan.read()
+        oracle.plan_step(s, xo, t, path, stalls, status)
+        xg = x.cpu().numpy().astype(np.float64)
+        print(f"step {t}: gpu {xg[0]}, oracle {xo[0]}, stalls {int(gstalls[0])}/{int(stalls[0])}")
+        assert int(stalls[0]) == 0 and int(gstalls[0]) == 0
+        assert np.array_equal(sts, status)
+        assert np.linalg.norm(xg - xo) <= 0.1 * 0.05, (t, xg, xo)  # direction within about 3 degrees
+        assert abs(gpath[0] - path[0]) <= 1e-6
+    del plan
+
+
+def test_eval_env_path_at_large_screening_reaches_the_source(B):
+    """Sec. VI-A at c = 10: with 1e5 walks per gradient and s = min(0.1, R/2)
+    the FP32 planning loop goes from x_start,1 to the unit impulse at (8, 0)."""
+    import torch
+    s = S.scene_eval_env(2, k_r=0.3, sigma=10.0, eps=1e-2, seed=0)
+    x = dev(np.array([[-8.0, 0.0]]), torch.float32)
+    plan = B.Plan(B.Domain(s), x, 100000, 10.0, s["eps"], 0.1, s["seed"])
+    steps = 0
+    while steps < 600:
+        plan.step(20)
+        steps += 20
+        if int(plan.read()[4][0]) != 0:
+            break
+    u, g, path, stalls, sts, step = plan.read()
+    xe = x.cpu().numpy()[0]
+    print(f"c=10: path length {float(path[0]):.2f}, status {int(sts[0])}, steps {int(step[0])}, "
+          f"stalls {int(stalls[0])}, end {xe}")
+    del plan
+    assert int(sts[0]) == 1, (sts, xe)
+    assert np.linalg.norm(xe - np.array([8.0, 0.0])) <= 0.1 + 1e-5
+    assert float(path[0]) >= 16.0 and int(stalls[0]) <= 20
