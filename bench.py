@@ -372,11 +372,11 @@ def eval_env_paths(B, torch, sigmas=(0.1, 1.0, 10.0), n_walks=100000, max_steps=
     """Screening and path length in the evaluation environment (Sec. VI-A,
     d = 2, k_r = 0.3, eps = 0.01): gradient ascent from x_start,1 = (-8, 0)
     to the unit impulse at (8, 0) with 1e5 walks per gradient and
-    s = min(0.1, d/2), for c = 0.1, 1 and 10.  The FP32 planning loop cannot
-    represent the weights at c = 10 over this distance: every step multiplies
-    the weight by 1 / I_0(sqrt(c) R), so a walk that reaches the source from
-    16 units away carries a weight below FP32's range and the gradient
-    estimate is 0 (the run stalls)."""
+    s = min(0.1, d/2), for c = 0.1, 1 and 10.  At c = 10 every walk that
+    reaches the source from 16 units away weighs below FP32's range (each step
+    multiplies the weight by 1 / I_0(sqrt(c) R)); the FP32 walk keeps the
+    weight's exponent apart and the planning graph steps along the direction
+    formed from the FP64 sums, so this run moves as the others do."""
     from paper_2406_01713_amd import scenes as S
     out = {"start": [-8.0, 0.0], "goal": [8.0, 0.0], "n_walks": n_walks, "s_ub": 0.1, "runs": {}}
     for c in sigmas:
