@@ -509,11 +509,35 @@ __device__ __forceinline__ void pair_round(cptr<float> rows, int n_cl, const uin
     }
 }
 
+// Inclusive prefix sum over the 64 lanes of a wave: DPP row shifts by 1, 2,
+// 4 and 8 sum within each row of 16 lanes, then the broadcasts of lane 15
+// (into rows 1 and 3) and lane 31 (into rows 2 and 3) carry the row totals.
+// Lanes whose source is outside the row or masked off add 0.  All lanes must
+// be active.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v)
+{
+    int x = (int)v;
+    x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);  // row_shr:1
+    x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);  // row_shr:2
+    x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);  // row_shr:4
+    x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);  // row_shr:8
+    x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);  // row_bcast:15
+    x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);  // row_bcast:31
+    return (uint32_t)x;
+}
+
 // Min over the members of the clusters each lane may need (thr as for
 // cluster_min), with the cluster test on the matrix cores and the members
 // scanned pair by pair.  Requires every lane of the wave to be active and
 // blocks of at most kMaxWavesPerBlock waves.  evals: member distances
 // evaluated by the wave.
+//
+// Per tile each lane gathers its 16 needs (bit 4 rt + r: walker 16 rt + 4 g +
+// r, g = lane / 16, needs cluster 16 t + lane % 16) into one mask; a wave
+// prefix sum of the popcounts gives every lane its queue slots, so a tile's
+// pairs are queued in one pass.  A tile whose pairs would overflow the queue
+// first evaluates the pairs already waiting, then goes row tile by row tile
+// (at most 4 x 64 pairs each).
 template <int D, bool BOX>
 __device__ __forceinline__ float cluster_min_pairs(cptr<float> rows, const float* __restrict__ mf, int n_cl,
                                                    const float (&x)[D], float thr, bool live, uint64_t& evals)
@@ -527,47 +551,62 @@ __device__ __forceinline__ float cluster_min_pairs(cptr<float> rows, const float
     mfma_walker_operands<D>(x, thr, live, A);
     const mf4* tab = reinterpret_cast<const mf4*>(mf) + lane;
     const int n_tiles = (n_cl + kMfmaTile - 1) / kMfmaTile;
-    const uint32_t wl = 4u * (uint32_t)(lane >> 4);
-    int qn = 0;  // queued pairs (wave-uniform), < 64 between ballots
-    uint32_t rounds = 0;
+    // queue entry: cluster << 6 | walker; the lane's own part of both
+    const uint32_t lane_e = ((uint32_t)(lane & (kMfmaTile - 1)) << 6) | (4u * (uint32_t)(lane >> 4));
+    int qn = 0;  // queued pairs (wave-uniform), < 64 between tiles
+    uint32_t pairs = 0;
     for (int t = 0; t < n_tiles; ++t) {
         const mf4 b = tab[t * kWave];
-        const uint32_t ctile = ((uint32_t)(t * kMfmaTile) + (uint32_t)(lane & (kMfmaTile - 1))) << 6;
+        // bits shift in from the top (rt = 3, r = 3 first), so no bit
+        // constants are needed
+        uint32_t nm = 0;
 #pragma unroll
-        for (int rt = 0; rt < 4; ++rt) {
+        for (int rt = 3; rt >= 0; --rt) {
             mf4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
             acc = __builtin_amdgcn_mfma_f32_16x16x4f32(A[0][rt], b[0], acc, 0, 0, 0);
             acc = __builtin_amdgcn_mfma_f32_16x16x4f32(A[1][rt], b[1], acc, 0, 0, 0);
             acc = __builtin_amdgcn_mfma_f32_16x16x4f32(A[2][rt], b[2], acc, 0, 0, 0);
-            bool need[4];
-            uint64_t bks[4];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                need[r] = !(acc[r] > 0.0f);  // NaN never skips
-                bks[r] = __ballot(need[r]);
+            for (int r = 3; r >= 0; --r) nm = nm + nm + (uint32_t)!(acc[r] > 0.0f);  // NaN never skips
+        }
+        uint32_t cnt = (uint32_t)__builtin_popcount(nm);
+        uint32_t incl = wave_incl_scan(cnt);
+        int total = __builtin_amdgcn_readlane((int)incl, kWave - 1);
+        uint32_t chunk = 0xFFFFu;  // the needs queued in this pass
+        if (qn + total > kPairCap) {
+            if (qn > 0) {
+                pair_round<D, BOX>(rows, n_cl, queue, 0, qn, x, best);
+                pairs += (uint32_t)qn;
+                qn = 0;
             }
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const uint64_t bk = bks[r];
-                if (bk) {  // wave-uniform
-                    if (need[r]) {
-                        const uint32_t pos = (uint32_t)qn + __builtin_amdgcn_mbcnt_hi(
-                                                                (uint32_t)(bk >> 32),
-                                                                __builtin_amdgcn_mbcnt_lo((uint32_t)bk, 0u));
-                        queue[pos] = ctile | (uint32_t)(16 * rt + r) | wl;
-                    }
-                    qn += __popcll(bk);
-                    if (qn >= kWave) {
-                        qn -= kWave;
-                        ++rounds;
-                        pair_round<D, BOX>(rows, n_cl, queue, qn, kWave, x, best);
-                    }
-                }
+            chunk = 0xFu;
+        }
+        const uint32_t tile_e = (uint32_t)(t * kMfmaTile) << 6;
+        for (;;) {  // wave-uniform: one pass, or one per row tile
+            uint32_t m = nm & chunk;
+            if (chunk != 0xFFFFu) {
+                cnt = (uint32_t)__builtin_popcount(m);
+                incl = wave_incl_scan(cnt);
+                total = __builtin_amdgcn_readlane((int)incl, kWave - 1);
             }
+            uint32_t pos = (uint32_t)qn + incl - cnt;
+            while (m) {  // per lane: its own needs, in bit order
+                const uint32_t bit = (uint32_t)__builtin_ctz(m);
+                m &= m - 1u;
+                queue[pos++] = (tile_e + lane_e) | (16u * (bit >> 2) + (bit & 3u));
+            }
+            qn += total;
+            while (qn >= kWave) {  // the last 64 queued go first
+                qn -= kWave;
+                pairs += kWave;
+                pair_round<D, BOX>(rows, n_cl, queue, qn, kWave, x, best);
+            }
+            if (chunk & 0x8000u) break;
+            chunk <<= 4;
         }
     }
     if (qn > 0) pair_round<D, BOX>(rows, n_cl, queue, 0, qn, x, best);
-    evals += ((uint64_t)rounds * kWave + (uint64_t)qn) * kCluster;
+    evals += ((uint64_t)pairs + (uint64_t)qn) * kCluster;
     return float_of_ord(best[lane]);
 }
 

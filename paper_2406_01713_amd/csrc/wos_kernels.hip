@@ -111,10 +111,11 @@ __device__ __forceinline__ void add_work(double (&a)[N], int at, const WorkCount
 }
 
 // ------------------------------------------------------------------------
-// Plain kernel.
+// Plain kernel.  FP32: at least 3 waves per SIMD (at most 168 registers per
+// lane); left free, the allocator may take a few more and fall to 2.
 // ------------------------------------------------------------------------
 template <typename T, int D, bool BWD, bool SRC>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kBlock, sizeof(T) == 4 ? 3 : 1)
 plain_kernel(const EnvP<T>* penv, const T* __restrict__ queries, int64_t n_units, int32_t chunks,
              int64_t n_walks, int64_t w_base, uint32_t q_base, const uint64_t* __restrict__ key_add,
              double* __restrict__ partials, double* __restrict__ records)

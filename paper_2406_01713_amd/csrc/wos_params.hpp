@@ -46,9 +46,10 @@ constexpr int kClusterMin = 64;
 // 9 = 1e30 (always skipped).
 // Pair-compacted member scan: (walker, cluster) pairs that the matrix-core
 // test keeps are queued per wave in LDS and evaluated 64 at a time, one pair
-// per lane.  The queue holds fewer than 64 pairs between rounds plus at most
-// one ballot's 64, so 128 entries never overflow.
-constexpr int kPairCap = 128;
+// per lane.  Between tiles fewer than 64 pairs wait; a tile adds its pairs in
+// one pass when they fit, else one row tile (at most 256) at a time after
+// the waiting ones are evaluated, so 320 entries never overflow.
+constexpr int kPairCap = 320;
 constexpr int kMaxWavesPerBlock = 4;  // every walk kernel runs <= 256 threads per block
 
 constexpr int kMfmaTile = 16;
