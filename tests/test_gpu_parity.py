@@ -401,6 +401,73 @@ def test_matrix_core_cull_matches_vector_cull(B):
     assert ma <= mc and ma <= mb
 
 
+def _dense_cloud(seed=21):
+    """d = 3: 1024 spheres (r 0.01-0.02) packed in [-0.5, 0.5]^3 plus 512
+    sparse ones (r 0.05-0.1) in the rest of the box [-3, 3]^3, no goal; g = 1
+    on obstacles.  Queries inside the cloud see every cloud cluster within
+    the outer-box distance, so all 64 walkers of a wave need every cluster of
+    a cloud tile: 1024 pairs per tile, more than the queue takes at once."""
+    rng = np.random.default_rng(seed)
+    d = 3
+    dense = rng.uniform(-0.5, 0.5, size=(1024, d))
+    sparse = []
+    while len(sparse) < 512:
+        p = rng.uniform(-2.8, 2.8, size=d)
+        if np.abs(p).max() > 0.8:
+            sparse.append(p)
+    c = np.concatenate([dense, np.array(sparse)])
+    r = np.concatenate([rng.uniform(0.01, 0.02, 1024), rng.uniform(0.05, 0.1, 512)])
+    s = S._empty(d)
+    s.update(sph_c=c, sph_r=r, d=d, goal_c=None, goal_r=None, outer=S.box_outer(d, 3.0),
+             bdata=S._bdata(0, d, g_goal=0.0, g_obs=1.0, g_outer=0.0), sigma=1.0, eps=1e-3,
+             n_walks=128, seed=seed, name="dense_cloud")
+    qs = []
+    while len(qs) < 4:
+        p = rng.uniform(-0.4, 0.4, size=d)
+        if S.is_clear(p, s, 0.005):
+            qs.append(p)
+    qs += [np.array([1.5, -1.2, 2.0]), np.array([-2.0, 1.0, -1.5])]
+    s["queries"] = np.array(qs)
+    return s
+
+
+def test_pair_queue_overflow_is_exact(B):
+    """A tile whose (walker, cluster) pairs overflow the per-wave queue is
+    queued row tile by row tile after the waiting pairs are evaluated: walks
+    and outputs stay bitwise those of the wave-uniform, vector-ALU and full
+    scans, in the plain, debug-walk and batched launches."""
+    s = _dense_cloud()
+    # precondition: at step 0 the 64 walkers of query 0 need more than
+    # 320 - 63 pairs in some tile (they all sit at the query point)
+    cl = B.wos_debug_clusters(3, s["sph_c"], s["sph_r"])["sph"][1]
+    x0 = s["queries"][0]
+    thr = np.min(np.minimum(x0 - s["outer"]["lo"], s["outer"]["hi"] - x0))
+    need = np.linalg.norm(cl[:, :3] - x0, axis=1) - cl[:, 3] <= thr
+    per_tile = [need[t:t + 16].sum() for t in range(0, len(need), 16)]
+    assert 64 * max(per_tile) > 320 - 63, per_tile
+    a = gpu_estimate(B, s)
+    for kw in (dict(full_scan=True), dict(wave_scan=True), dict(scalar_cull=True)):
+        b = gpu_estimate(B, s, **kw)
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y), kw
+    dom = B.Domain(s)
+    for q in (0, 1, 4):
+        ra = B.wos_debug_walks(dom, s["queries"][q], q, 0, 128, s["sigma"], s["eps"], s["seed"],
+                               opt=B.options())
+        rb = B.wos_debug_walks(dom, s["queries"][q], q, 0, 128, s["sigma"], s["eps"], s["seed"],
+                               opt=B.options(full_scan=True))
+        assert np.array_equal(ra, rb), q
+    envs = [s, S.scene_c4_env(3, n_walks=128, seed=4, q_cap=6)]
+    rng = np.random.default_rng(12)
+    ubar = rng.normal(size=sum(len(e["queries"]) for e in envs)).astype(np.float32)
+    a = gpu_batch(B, envs, 128, 5, ubar=ubar)
+    b = gpu_batch(B, envs, 128, 5, ubar=ubar, full_scan=True)
+    for k in ("u", "g", "dx", "ds", "dg"):
+        assert np.array_equal(a[k], b[k]), k
+    assert np.array_equal(a["st"][:, :12], b["st"][:, :12])
+    assert np.all(a["u"][:4] > 0)  # the cloud absorbs walks
+
+
 def test_batch_vs_oracle(B, oracle):
     envs = _ragged(n_envs=6, q_cap=4, n_walks=256)
     out = gpu_batch(B, envs, 256, 7)
