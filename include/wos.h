@@ -205,6 +205,9 @@ int wos_domain_dim(const wos_domain* dom);
  *             se = sample standard deviation / sqrt(n_walks)
  *   opt       NULL for defaults
  * Plain form: one walk per lane, lanes idle once their walk ends.
+ * FP32 walks keep the weight product's binary exponent apart and sum in FP64,
+ * so walks whose weight is below FP32's range still count; a mean below it
+ * reads as 0 in FP32 out_u / out_grad (out_stats are FP64).
  * Errors: WOS_EINVAL, WOS_ENOTSUP (affine data with sigma != 0; plane wave
  * with |k|^2 != sigma; sigma R^2 too large for the weight series), WOS_EHIP.
  */
@@ -278,9 +281,12 @@ int wos_estimate_batch(const wos_domain* const* envs, int n_envs, const float* q
  * of [fused forward + backward walk kernel, finalize, update] on `stream`.
  *   x      device float, S x d start points, updated in place each step
  *   Step t uses key seed + t (t kept on the device, so replays need no host
- *   work); start s is query s of the walks.  A start whose estimated gradient
- *   is exactly zero does not move (a stall is counted); a start within eps of
- *   the boundary stops (status 1 at the goal, 2 elsewhere).
+ *   work); start s is query s of the walks.  The step direction is the unit
+ *   vector of the gradient's FP64 walk sums, so it exists even where the mean
+ *   gradient is below FP32's range (long distances at large sigma).  A start
+ *   whose estimated gradient is exactly zero does not move (a stall is
+ *   counted); a start within eps of the boundary stops (status 1 at the goal,
+ *   2 elsewhere).
  * The plan owns its scratch buffers; x must outlive the plan.
  */
 int wos_plan_create(const wos_domain* dom, float* x, int64_t n_starts, int64_t n_walks,
@@ -292,9 +298,10 @@ int wos_plan_step(wos_plan* plan, int n_steps);
 
 /*
  * wos_plan_buffers -- device pointers owned by the plan (valid until destroy):
- *   u [S] float, grad [S x 8] float (last step's estimates, first d columns), path_len [S]
- *   double (sum of step lengths), stalls [S] int32, status [S] int32,
- *   step [1] uint64 (steps taken).  Any output pointer may be NULL.
+ *   u [S] float, grad [S x 8] float (last step's estimates, first d columns;
+ *   values below FP32's range read as 0), path_len [S] double (sum of step
+ *   lengths), stalls [S] int32, status [S] int32, step [1] uint64 (steps
+ *   taken).  Any output pointer may be NULL.
  */
 int wos_plan_buffers(wos_plan* plan, float** u, float** grad, double** path_len,
                      int32_t** stalls, int32_t** status, uint64_t** step);
