@@ -35,7 +35,8 @@ def rel_bound(sigma, k):
 def test_tiny_weights_match_the_oracle(B, oracle, d):
     """sigma = 100: a quarter of the walks that reach the source carry a
     weight below 2^-126; FP32 walks keep them, nonzero and within the drift
-    bound of the FP64 walk."""
+    bound of the FP64 walk, and so are the walk's d u_hat / d sigma and its
+    sum of d ln C / d sigma."""
     q = np.zeros((3, d))
     q[:, :2] = [[2.0, 0.5], [4.0, 2.0], [5.0, 3.5]]
     s = S.scene_eval_env(d, k_r=0.3, sigma=100.0, eps=1e-2, queries=q, n_walks=256, seed=0)
@@ -60,10 +61,15 @@ def test_tiny_weights_match_the_oracle(B, oracle, d):
             gs = np.abs(r["grad"]).max()
             eu = abs(rec[w, 0] - r["u"]) / r["u"]
             eg = np.abs(rec[w, 1:1 + d] - r["grad"]).max() / gs
-            worst.append((max(eu, eg) / tol, eu, eg, r["steps"], r["u"], qi, w))
+            # backward record: d u_hat / d sigma (weighted, so scaled like u)
+            # and the unweighted sum of d ln C / d sigma
+            ed = abs(rec[w, d + 6] - r["du_dsigma"]) / abs(r["du_dsigma"])
+            es = abs(rec[w, d + 1] - r["dlnC_sum"]) / max(abs(r["dlnC_sum"]), 1e-30)
+            worst.append((max(eu, eg, ed, es) / tol, eu, eg, ed, es, r["steps"], r["u"], qi, w))
     worst.sort(reverse=True)
     for t in worst[:4]:
-        print("error / bound %.3f: rel u %.2e, rel grad %.2e, steps %d, u %.3e (query %d, walk %d)" % t)
+        print("error / bound %.3f: rel u %.2e, grad %.2e, du/dsigma %.2e, S %.2e; steps %d, u %.3e "
+              "(query %d, walk %d)" % t)
     assert worst and worst[0][0] <= 1.0, worst[:4]
     assert same >= 0.8 * n * len(q), same
     assert tiny >= 8, tiny
