@@ -679,9 +679,13 @@ void plan_batch(const wos_domain* const* envs, const int64_t* q_off, int n_envs,
     L.grid = std::max(1, resident_blocks * t.grid_mult);
     const int64_t waves = (int64_t)L.grid * (block / kWave);
     const int64_t target = waves * t.units_per_wave;
-    // one walk-range length for the launch: total walks / target units,
-    // a multiple of the wave width, at least 256 walks (4 per lane)
-    int64_t wps = std::max<int64_t>(256, sumQW / std::max<int64_t>(target, 1));
+    // one walk-range length for the launch: total walks / target units, a
+    // multiple of the wave width, at least 128 walks (2 per lane, so lanes
+    // refill).  Measured: on the 7-D planning step (524288 walks, 4096
+    // resident waves) 128 beat 256 by 25 % (half the waves had been idle) and
+    // 64 by 7 %; on one-start planning with 1e5 walks 128 beat 64 by 5-20 %
+    // (a wave with one walk per lane waits for its longest of 64 walks).
+    int64_t wps = std::max<int64_t>(2 * kWave, sumQW / std::max<int64_t>(target, 1));
     wps = std::min(wps, maxW);
     wps = ((wps + kWave - 1) / kWave) * kWave;
 
