@@ -211,19 +211,19 @@ class Plain:
         return [b["u"] for b in self.bufs]
 
 
-def traffic_entry(khash):
-    """HBM bytes per launch from the committed counter summary, if it was
-    taken on the current kernel sources."""
+def counter_entry(khash):
+    """The committed counter summary of the d = 7 launch (HBM bytes per launch,
+    VALU busy fraction), if it was taken on the current kernel sources."""
     path = os.path.join(ROOT, "profiles", "traffic_persistent_d7.json")
     if not os.path.exists(path):
-        return None
+        return {}
     try:
         t = json.load(open(path))
     except (OSError, ValueError):
-        return None
+        return {}
     if t.get("kernel_hash") != khash:
-        return None
-    return t.get("bytes_per_launch")
+        return {}
+    return t
 
 
 def near_goal_starts(s, n, seed=5):
@@ -485,7 +485,7 @@ def main():
     value = walk_steps / (ms_step / 1e3)
     achieved = flops / (launch_ms / 1e3) / 1e12
     khash = kernel_hash()
-    traffic = traffic_entry(khash)
+    counters = counter_entry(khash)
     ceilings = {}
     try:
         fma, _ = B.wos_microbench(0)
@@ -511,7 +511,11 @@ def main():
                                        "cluster-culled (exact: same walks as a full scan)"},
            "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
                         "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
-                        "traffic": traffic,
+                        "traffic": counters.get("bytes_per_launch"),
+                        "valu_busy": counters.get("valu_busy"),
+                        "valu_busy_basis": "share of cycles the vector ALUs issue (SQ_ACTIVE_INST_VALU, "
+                                           "rocprofv3 on these kernel sources); achieved/frac count only the "
+                                           "distance arithmetic of the executed obstacle tests",
                         "kernel": "persistent_kernel<fused fwd+bwd>",
                         "launch_ms": launch_ms,
                         "flops_per_launch": flops,
