@@ -502,9 +502,13 @@ def test_autotune_writes_cache_and_batch_uses_it(B):
 
 # ------------------------------------------------------------ planning ----
 
-def test_plan_graph_matches_oracle_steps(B, oracle):
+@pytest.mark.parametrize("n_walks", [512, 2048])
+def test_plan_graph_matches_oracle_steps(B, oracle, n_walks):
+    """Three captured planning steps on the full C5 scene (512 spheres + 512
+    boxes) from four starts near the goal follow the oracle's steps; 2048
+    walks per gradient is the benchmark's planning configuration."""
     import torch
-    s = S.scene_c5(n_starts=3, n_walks=512)
+    s = S.scene_c5(n_starts=3, n_walks=n_walks)
     rng = np.random.default_rng(3)
     starts = []
     while len(starts) < 4:
@@ -515,7 +519,7 @@ def test_plan_graph_matches_oracle_steps(B, oracle):
     x0 = np.array(starts)
     x = dev(x0, torch.float32)
     dom = B.Domain(s)
-    plan = B.Plan(dom, x, 512, s["sigma"], s["eps"], s["s_ub"], s["seed"])
+    plan = B.Plan(dom, x, n_walks, s["sigma"], s["eps"], s["s_ub"], s["seed"])
     xo = np.ascontiguousarray(x0.astype(np.float32).astype(np.float64))
     path = np.zeros(4)
     stalls = np.zeros(4, dtype=np.int32)
