@@ -318,10 +318,11 @@ int wos_plan_read(wos_plan* plan, float* u, float* grad, double* path_len, int32
 void wos_plan_destroy(wos_plan* plan);
 
 /*
- * wos_autotune -- time the persistent kernel's launch shapes on a synthetic
- * scene of dimension d with M sphere obstacles and Q queries, and record the
- * fastest in the cache file (JSON, created or updated) under the bucket of
- * (d, M, Q).  Subsequent batched launches in this process read the cache at
+ * wos_autotune -- time the persistent kernel's launch shapes (work units per
+ * resident wave 1-16, grid of 1 or 2 times the resident blocks, at least 1, 2
+ * or 4 walks per lane in a unit) on a synthetic scene of dimension d with M
+ * sphere obstacles and Q queries, and record the fastest in the cache file
+ * (JSON, created or updated) under the bucket of (d, M, Q).  Subsequent batched launches in this process read the cache at
  * cache_path (or $WOS_AUTOTUNE_CACHE when wos_set_autotune_cache was not
  * called).  Blocks the calling thread (synchronises the device).
  */

@@ -566,6 +566,7 @@ int upload(void* dst, const void* src, size_t bytes, hipStream_t st)
 struct Tune {
     int units_per_wave = 4;
     int grid_mult = 1;
+    int walks_per_lane = 2;  // least walks per lane in a work unit (lane refill needs 2)
 };
 std::mutex g_tune_mu;
 std::map<std::string, Tune> g_tune;
@@ -600,11 +601,12 @@ void load_tune_locked(const char* path)
     char line[256];
     while (fgets(line, sizeof(line), f)) {
         char key[64];
-        int upw = 0, gm = 0;
-        // one entry per line: "key": {"units_per_wave": U, "grid_mult": G},
-        if (sscanf(line, " \"%63[^\"]\": {\"units_per_wave\": %d, \"grid_mult\": %d}", key, &upw, &gm) == 3 &&
-            upw > 0 && gm > 0)
-            g_tune[key] = Tune{upw, gm};
+        int upw = 0, gm = 0, wpl = 2;
+        // one entry per line: "key": {"units_per_wave": U, "grid_mult": G, "walks_per_lane": W},
+        // (W absent in older files: 2)
+        const int n = sscanf(line, " \"%63[^\"]\": {\"units_per_wave\": %d, \"grid_mult\": %d, \"walks_per_lane\": %d}",
+                             key, &upw, &gm, &wpl);
+        if (n >= 3 && upw > 0 && gm > 0 && wpl > 0 && wpl <= 64) g_tune[key] = Tune{upw, gm, n == 4 ? wpl : 2};
     }
     fclose(f);
 }
@@ -625,8 +627,9 @@ int save_tune_locked(const char* path)
     fprintf(f, "{\n");
     size_t i = 0;
     for (auto& kv : g_tune) {
-        fprintf(f, "  \"%s\": {\"units_per_wave\": %d, \"grid_mult\": %d}%s\n", kv.first.c_str(),
-                kv.second.units_per_wave, kv.second.grid_mult, (++i < g_tune.size()) ? "," : "");
+        fprintf(f, "  \"%s\": {\"units_per_wave\": %d, \"grid_mult\": %d, \"walks_per_lane\": %d}%s\n",
+                kv.first.c_str(), kv.second.units_per_wave, kv.second.grid_mult, kv.second.walks_per_lane,
+                (++i < g_tune.size()) ? "," : "");
     }
     fprintf(f, "}\n");
     fclose(f);
@@ -654,7 +657,7 @@ struct BatchLayout {
 // launch has about units_per_wave units per resident wave; envs are ordered
 // by decreasing unit cost (longest-processing-time first).
 void plan_batch(const wos_domain* const* envs, const int64_t* q_off, int n_envs, const int64_t* n_walks,
-                int q_stride, int force_upw, int force_gm, bool full_scan, bool src, BatchLayout& L)
+                int q_stride, int force_upw, int force_gm, int force_wpl, bool full_scan, bool src, BatchLayout& L)
 {
     const int block = 256;
     int64_t sumQW = 0, maxM = 0, heavyQ = 0, maxW = 1;
@@ -675,17 +678,19 @@ void plan_batch(const wos_domain* const* envs, const int64_t* q_off, int n_envs,
     Tune t = lookup_tune(heavy_d, maxM, heavyQ);
     if (force_upw > 0) t.units_per_wave = force_upw;
     if (force_gm > 0) t.grid_mult = force_gm;
+    if (force_wpl > 0) t.walks_per_lane = force_wpl;
     const int resident_blocks = persistent_resident_blocks(true, src, block);
     L.grid = std::max(1, resident_blocks * t.grid_mult);
     const int64_t waves = (int64_t)L.grid * (block / kWave);
     const int64_t target = waves * t.units_per_wave;
     // one walk-range length for the launch: total walks / target units, a
-    // multiple of the wave width, at least 128 walks (2 per lane, so lanes
-    // refill).  Measured: on the 7-D planning step (524288 walks, 4096
-    // resident waves) 128 beat 256 by 25 % (half the waves had been idle) and
-    // 64 by 7 %; on one-start planning with 1e5 walks 128 beat 64 by 5-20 %
-    // (a wave with one walk per lane waits for its longest of 64 walks).
-    int64_t wps = std::max<int64_t>(2 * kWave, sumQW / std::max<int64_t>(target, 1));
+    // multiple of the wave width, at least walks_per_lane walks per lane
+    // (default 2, so lanes refill).  Measured: on the 7-D planning step
+    // (524288 walks, 4096 resident waves) 2 per lane beat 4 by 25 % (half the
+    // waves had been idle) and 1 by 7 %; on one-start planning with 1e5 walks
+    // 2 beat 1 by 5-20 % (a wave with one walk per lane waits for its longest
+    // of 64 walks).
+    int64_t wps = std::max<int64_t>((int64_t)t.walks_per_lane * kWave, sumQW / std::max<int64_t>(target, 1));
     wps = std::min(wps, maxW);
     wps = ((wps + kWave - 1) / kWave) * kWave;
 
@@ -723,7 +728,8 @@ void plan_batch(const wos_domain* const* envs, const int64_t* q_off, int n_envs,
 int run_batch(const wos_domain* const* envs, int n_envs, const float* queries, const int64_t* q_offsets,
               const double* sigma, const double* eps, const int64_t* n_walks, uint64_t seed, float* out_u,
               float* out_grad, double* out_stats, const float* grad_u, float* out_dx, double* out_dsigma,
-              double* out_dg, const wos_options* opt, hipStream_t st, int force_upw, int force_gm)
+              double* out_dg, const wos_options* opt, hipStream_t st, int force_upw, int force_gm,
+              int force_wpl)
 {
     wos_options o;
     int rc = read_opts(opt, o);
@@ -755,7 +761,8 @@ int run_batch(const wos_domain* const* envs, int n_envs, const float* queries, c
     }
 
     BatchLayout L;
-    plan_batch(envs, q_offsets, n_envs, n_walks, kBatchStride, force_upw, force_gm, (o.flags & WOS_FULL_SCAN) != 0, src,
+    plan_batch(envs, q_offsets, n_envs, n_walks, kBatchStride, force_upw, force_gm, force_wpl,
+               (o.flags & WOS_FULL_SCAN) != 0, src,
                L);
 
     Scratch S(st);
@@ -1171,7 +1178,7 @@ int wos_estimate_batch(const wos_domain* const* envs, int n_envs, const float* q
                        double* out_dg, const wos_options* opt, void* stream)
 {
     return run_batch(envs, n_envs, queries, q_offsets, sigma, eps, n_walks, seed, out_u, out_grad, out_stats,
-                     grad_u, out_dx, out_dsigma, out_dg, opt, (hipStream_t)stream, 0, 0);
+                     grad_u, out_dx, out_dsigma, out_dg, opt, (hipStream_t)stream, 0, 0, 0);
 }
 
 int wos_debug_walks(const wos_domain* D, const double* query, uint32_t q_index, int64_t w0, int64_t n, double sigma,
@@ -1310,7 +1317,7 @@ int wos_plan_create(const wos_domain* D, float* x, int64_t n_starts, int64_t n_w
     const int64_t qoff[2] = {0, n_starts};
     const int64_t nw[1] = {n_walks};
     BatchLayout L;
-    plan_batch(envs, qoff, 1, nw, D->d, 0, 0, (o.flags & WOS_FULL_SCAN) != 0, D->has_src, L);
+    plan_batch(envs, qoff, 1, nw, D->d, 0, 0, 0, (o.flags & WOS_FULL_SCAN) != 0, D->has_src, L);
     const int64_t S = n_starts;
     if (e == hipSuccess) e = hipMalloc(&P->u, S * sizeof(float));
     if (e == hipSuccess) e = hipMalloc(&P->grad, S * kBatchStride * sizeof(float));
@@ -1459,18 +1466,20 @@ int wos_autotune(int d, int64_t M, int64_t Q, int64_t n_walks, const char* cache
     float best_ms = INFINITY;
     const int upws[] = {1, 2, 4, 8, 16};
     const int gms[] = {1, 2};
+    const int wpls[] = {1, 2, 4};
     const wos_domain* envs[1] = {D};
     const int64_t qoff[2] = {0, Q};
     const int64_t nw[1] = {n_walks};
     const double sig = 2.0, ep = 1e-4;
-    for (int gm : gms) {
+    for (int wpl : wpls) {
+        for (int gm : gms) {
         for (int upw : upws) {
             if (e != hipSuccess || rc) break;
             // warm-up then one timed launch
             for (int rep = 0; rep < 2 && !rc && e == hipSuccess; ++rep) {
                 if (rep == 1) e = hipEventRecord(e0, nullptr);
                 rc = run_batch(envs, 1, dq, qoff, &sig, &ep, nw, 1234 + rep, du, dgr, nullptr, dub, ddx, dds, ddg,
-                               nullptr, nullptr, upw, gm);
+                               nullptr, nullptr, upw, gm, wpl);
                 if (rep == 1 && e == hipSuccess) e = hipEventRecord(e1, nullptr);
             }
             if (e == hipSuccess && !rc) e = hipEventSynchronize(e1);
@@ -1478,8 +1487,9 @@ int wos_autotune(int d, int64_t M, int64_t Q, int64_t n_walks, const char* cache
             if (e == hipSuccess && !rc) e = hipEventElapsedTime(&ms, e0, e1);
             if (e == hipSuccess && !rc && ms < best_ms) {
                 best_ms = ms;
-                best = Tune{upw, gm};
+                best = Tune{upw, gm, wpl};
             }
+        }
         }
     }
     if (e0) (void)hipEventDestroy(e0);

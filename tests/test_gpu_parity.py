@@ -491,7 +491,7 @@ def test_autotune_writes_cache_and_batch_uses_it(B):
         path = os.path.join(td, "tune.json")
         B.wos_autotune(7, 64, 32, 256, path)
         txt = open(path).read()
-        assert "units_per_wave" in txt and "d7_" in txt
+        assert "units_per_wave" in txt and "walks_per_lane" in txt and "d7_" in txt
         B.wos_set_autotune_cache(path)
         envs = _ragged(n_envs=3, q_cap=8, n_walks=256)
         a = gpu_batch(B, envs, 256, 5)
