@@ -72,6 +72,9 @@ extern "C" {
 #define WOS_WAVE_SCAN 8u   /* FP32: every lane scans the members of every cluster
                               some lane of its wave needs, instead of queuing the
                               needed (walker, cluster) pairs; same walks */
+#define WOS_OUT_FP64 16u   /* wos_estimate with FP32 walks: out_u and out_grad are
+                              double, the FP64 walk sums without rounding to FP32
+                              (means below FP32's range stay); other calls reject it */
 
 /* boundary-data modes */
 #define WOS_BDATA_CLASS 0  /* g_goal / g_obstacle / g_outer per component */
@@ -198,8 +201,8 @@ int wos_domain_dim(const wos_domain* dom);
  *   sigma     screening coefficient c = 1/t >= 0
  *   eps       absorption shell width > 0
  *   seed      Philox key
- *   out_u     device, Q (same type as queries)
- *   out_grad  device, Q x d, or NULL
+ *   out_u     device, Q (same type as queries; double with WOS_OUT_FP64)
+ *   out_grad  device, Q x d, or NULL (same type as out_u)
  *   out_stats device double, Q x (d + 4), or NULL: per query
  *             [se_u, se_grad[0..d-1], mean_steps, n_truncated, n_degenerate],
  *             se = sample standard deviation / sqrt(n_walks)
@@ -207,7 +210,8 @@ int wos_domain_dim(const wos_domain* dom);
  * Plain form: one walk per lane, lanes idle once their walk ends.
  * FP32 walks keep the weight product's binary exponent apart and sum in FP64,
  * so walks whose weight is below FP32's range still count; a mean below it
- * reads as 0 in FP32 out_u / out_grad (out_stats are FP64).
+ * reads as 0 in FP32 out_u / out_grad (out_stats are FP64) unless WOS_OUT_FP64
+ * asks for double outputs.
  * Errors: WOS_EINVAL, WOS_ENOTSUP (affine data with sigma != 0; plane wave
  * with |k|^2 != sigma; sigma R^2 too large for the weight series), WOS_EHIP.
  */

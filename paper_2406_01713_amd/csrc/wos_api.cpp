@@ -485,7 +485,7 @@ int read_opts(const wos_options* opt, wos_options& o)
 {
     o = wos_options{WOS_FP32, 0u, 0u, 0u};
     if (opt) o = *opt;
-    if (o.flags & ~(WOS_FP64 | WOS_FULL_SCAN | WOS_SCALAR_CULL | WOS_WAVE_SCAN))
+    if (o.flags & ~(WOS_FP64 | WOS_FULL_SCAN | WOS_SCALAR_CULL | WOS_WAVE_SCAN | WOS_OUT_FP64))
         return fail(WOS_EINVAL, "unknown flags 0x%x", o.flags);
     if (o.reserved != 0) return fail(WOS_EINVAL, "wos_options.reserved must be 0");
     return WOS_OK;
@@ -735,6 +735,7 @@ int run_batch(const wos_domain* const* envs, int n_envs, const float* queries, c
     int rc = read_opts(opt, o);
     if (rc) return rc;
     if (o.flags & WOS_FP64) return fail(WOS_ENOTSUP, "the batched kernel computes in FP32 only");
+    if (o.flags & WOS_OUT_FP64) return fail(WOS_ENOTSUP, "WOS_OUT_FP64 applies to wos_estimate only");
     if (n_envs < 0 || (n_envs > 0 && (!envs || !q_offsets || !sigma || !eps || !n_walks)))
         return fail(WOS_EINVAL, "envs, q_offsets, sigma, eps and n_walks are required");
     if (n_envs == 0) return WOS_OK;
@@ -1016,6 +1017,7 @@ int wos_varadhan(const void* u, const void* grad_u, int64_t n, int d, int stride
     wos_options o;
     int rc = read_opts(opt, o);
     if (rc) return rc;
+    if (o.flags & WOS_OUT_FP64) return fail(WOS_ENOTSUP, "WOS_OUT_FP64 applies to wos_estimate only (pass WOS_FP64 for double u)");
     if (n < 0) return fail(WOS_EINVAL, "n < 0");
     if (!(sigma > 0.0) || !std::isfinite(sigma)) return fail(WOS_EINVAL, "sigma must be finite and > 0 (t = 1/sigma)");
     if (n > 0 && (!u || !out_w)) return fail(WOS_EINVAL, "u and out_w are required");
@@ -1094,6 +1096,7 @@ static int estimate_impl(const wos_domain* D, const void* queries, int64_t Q, in
         return fail(WOS_EINVAL, "out_u is required");
     }
     if (Q > 0 && !queries) return fail(WOS_EINVAL, "queries is NULL");
+    if (bwd && (o.flags & WOS_OUT_FP64)) return fail(WOS_ENOTSUP, "WOS_OUT_FP64 applies to wos_estimate only");
     if (bwd && D->has_src && !(sigma > 0.0))
         return fail(WOS_ENOTSUP, "the sigma derivative of a point source is provided for sigma > 0 only");
     const int d = D->d;
@@ -1148,9 +1151,14 @@ static int estimate_impl(const wos_domain* D, const void* queries, int64_t Q, in
         WOS_HIP(launch_plain<float>(d, bwd, D->has_src, pd, (const float*)queries, Q, n_walks, 0, 0, nullptr, partials,
                                     nullptr, st),
                 "plain walk kernel");
-        WOS_HIP(launch_finalize_plain<float>(d, bwd, partials, Q, chunks, n_walks, uo, (float*)out_grad, out_stats,
-                                             (const float*)grad_u, (float*)out_dx, out_dq, prod, st),
-                "finalize");
+        if (o.flags & WOS_OUT_FP64)  // forward only: the FP64 sums written without rounding to FP32
+            WOS_HIP(launch_finalize_plain<double>(d, false, partials, Q, chunks, n_walks, (double*)out_u,
+                                                  (double*)out_grad, out_stats, nullptr, nullptr, nullptr, nullptr, st),
+                    "finalize");
+        else
+            WOS_HIP(launch_finalize_plain<float>(d, bwd, partials, Q, chunks, n_walks, uo, (float*)out_grad, out_stats,
+                                                 (const float*)grad_u, (float*)out_dx, out_dq, prod, st),
+                    "finalize");
     }
     if (bwd) WOS_HIP(launch_reduce_pairs(prod, Q, out_dsigma, out_dg, st), "reduce");
     return WOS_OK;
@@ -1188,6 +1196,7 @@ int wos_debug_walks(const wos_domain* D, const double* query, uint32_t q_index, 
     wos_options o;
     int rc = read_opts(opt, o);
     if (rc) return rc;
+    if (o.flags & WOS_OUT_FP64) return fail(WOS_ENOTSUP, "WOS_OUT_FP64 applies to wos_estimate only");
     if ((rc = check_device(D))) return rc;
     if (n < 1 || w0 < 0 || w0 + n > ((int64_t)1 << 32)) return fail(WOS_EINVAL, "bad walk range");
     const int d = D->d;
@@ -1294,6 +1303,7 @@ int wos_plan_create(const wos_domain* D, float* x, int64_t n_starts, int64_t n_w
     int rc = read_opts(opt, o);
     if (rc) return rc;
     if (o.flags & WOS_FP64) return fail(WOS_ENOTSUP, "the planning loop computes in FP32 only");
+    if (o.flags & WOS_OUT_FP64) return fail(WOS_ENOTSUP, "WOS_OUT_FP64 applies to wos_estimate only");
     if ((rc = check_device(D))) return rc;
     if (n_starts < 1 || n_starts > (1 << 24)) return fail(WOS_EINVAL, "n_starts out of range");
     if (n_walks < 1 || n_walks > ((int64_t)1 << 31)) return fail(WOS_EINVAL, "n_walks must be in [1, 2^31]");

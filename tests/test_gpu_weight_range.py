@@ -123,3 +123,47 @@ def test_eval_env_path_at_large_screening_reaches_the_source(B):
     assert int(sts[0]) == 1, (sts, xe)
     assert np.linalg.norm(xe - np.array([8.0, 0.0])) <= 0.1 + 1e-5
     assert float(path[0]) >= 16.0 and int(stalls[0]) <= 20
+
+
+def test_fp64_outputs_keep_means_below_fp32_range(B, oracle):
+    """WOS_OUT_FP64: FP32 walks, FP64 u and grad.  At sigma = 100 the mean
+    from x_start,1 (about 1e-150) reads as 0 in FP32 outputs but stays in
+    FP64 outputs and agrees with the FP64 oracle on the same walks; where the
+    mean is in FP32's range the two outputs agree after rounding; the
+    Varadhan read-out of the FP64 output is finite and matches the oracle's.
+    Calls other than wos_estimate reject the flag."""
+    import torch
+    q = np.array([[-8.0, 0.0], [-6.0, 1.0], [6.5, 1.0]])
+    s = S.scene_eval_env(2, k_r=0.3, sigma=100.0, eps=1e-2, queries=q, n_walks=16384, seed=0)
+    dom = B.Domain(s)
+    x = torch.as_tensor(q, dtype=torch.float32, device="cuda")
+    u32 = torch.empty(3, device="cuda")
+    g32 = torch.empty(3, 2, device="cuda")
+    u64 = torch.empty(3, dtype=torch.float64, device="cuda")
+    g64 = torch.empty(3, 2, dtype=torch.float64, device="cuda")
+    st = torch.empty(3, 6, dtype=torch.float64, device="cuda")
+    B.wos_estimate(dom, x, s["n_walks"], s["sigma"], s["eps"], s["seed"], u32, g32)
+    B.wos_estimate(dom, x, s["n_walks"], s["sigma"], s["eps"], s["seed"], u64, g64, st,
+                   opt=B.options(out_fp64=True))
+    torch.cuda.synchronize()
+    a32, a64 = u32.cpu().numpy(), u64.cpu().numpy()
+    uc, gc, stc = oracle.estimate(s)
+    print("u fp32 out", a32, "fp64 out", a64, "oracle", uc)
+    assert a32[0] == 0.0 and 0.0 < a64[0] < 1e-100
+    # same walks as the oracle: FP32 drift only (from (6.5, 1) every first
+    # ball holds the source, so the SE there is below FP32 rounding)
+    assert np.all(uc > 0) and np.all(np.abs(a64 - uc) <= np.maximum(4 * stc[:, 0], 1e-5 * uc)), (a64, uc, stc[:, 0])
+    assert np.all(np.abs(a64 - uc) <= 1e-3 * uc), (a64, uc)
+    assert a32[2] > 1e-30 and np.float32(a64[2]) == a32[2]
+    assert np.array_equal(g64.cpu().numpy().astype(np.float32)[2], g32.cpu().numpy()[2])
+    w = torch.empty(3, dtype=torch.float64, device="cuda")
+    B.wos_varadhan(u64, s["sigma"], out_w=w, opt=B.options(fp64=True))
+    torch.cuda.synchronize()
+    wo = -np.sqrt(1.0 / s["sigma"]) * np.log(uc)
+    assert np.all(np.isfinite(w.cpu().numpy())) and np.allclose(w.cpu().numpy(), wo, rtol=0, atol=5e-3), (w, wo)
+    with pytest.raises(B.WosError):
+        B.wos_backward(dom, x, 64, s["sigma"], s["eps"], 0, torch.ones(3, device="cuda"),
+                       torch.empty(3, 2, device="cuda"), torch.empty(1, dtype=torch.float64, device="cuda"),
+                       torch.empty(1, dtype=torch.float64, device="cuda"), opt=B.options(out_fp64=True))
+    with pytest.raises(B.WosError):
+        B.Plan(dom, x.clone(), 64, s["sigma"], s["eps"], 0.1, 0, opt=B.options(out_fp64=True))
