@@ -457,30 +457,53 @@ finalize_batch(const BatchEnv* __restrict__ benv, const double* __restrict__ par
     const int d = be.d;
     const double n = (double)be.n_walks;
     double bs = 0.0, bg = 0.0;
-    for (int ql = threadIdx.x; ql < be.n_q; ql += kBlock) {
+    // a thread per query, or, with 64 or more walk ranges per query (one
+    // planning start with 1e5 walks has about 800), a wave per query whose
+    // lanes stride over the ranges and are then summed across the wave
+    const bool by_wave = be.splits >= kWave;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int q0 = by_wave ? (int)(threadIdx.x / kWave) : (int)threadIdx.x;
+    const int dq = by_wave ? kBlock / kWave : kBlock;
+    for (int ql = q0; ql < be.n_q; ql += dq) {  // wave-uniform when by_wave
         double a[kNAccBatch];
+#pragma unroll
         for (int i = 0; i < kNAccBatch; ++i) a[i] = 0.0;
         const double* row = partials + (be.unit_off + (int64_t)ql * be.splits) * kNAccBatch;
-        for (int c = 0; c < be.splits; ++c)
-            for (int i = 0; i < kNAccBatch; ++i) a[i] += row[c * kNAccBatch + i];
+        if (by_wave) {
+            for (int c = lane; c < be.splits; c += kWave)
+#pragma unroll
+                for (int i = 0; i < kNAccBatch; ++i) a[i] += row[c * kNAccBatch + i];
+#pragma unroll
+            for (int i = 0; i < kNAccBatch; ++i) a[i] = wave_sum(a[i]);
+            if (lane != 0) continue;
+        } else {
+            for (int c = 0; c < be.splits; ++c)
+#pragma unroll
+                for (int i = 0; i < kNAccBatch; ++i) a[i] += row[c * kNAccBatch + i];
+        }
         const int64_t qg = be.q_off + ql;
         out_u[qg] = (float)(a[0] / n);
         // partial rows use the 8-wide layout of nacc(kMaxDim)
         constexpr int M = kMaxDim;
         if (out_grad)
+#pragma unroll
             for (int i = 0; i < M; ++i) out_grad[qg * grad_stride + i] = (i < d) ? (float)(a[2 + i] / n) : 0.0f;
         if (out_dir) {  // unit direction from the FP64 sums, scaled by the largest entry first
             double m = 0.0, g2 = 0.0;
-            for (int i = 0; i < d; ++i) m = ::fmax(m, ::fabs(a[2 + i]));
+#pragma unroll
+            for (int i = 0; i < M; ++i) m = (i < d) ? ::fmax(m, ::fabs(a[2 + i])) : m;
             if (m > 0.0)
-                for (int i = 0; i < d; ++i) g2 += (a[2 + i] / m) * (a[2 + i] / m);
+#pragma unroll
+                for (int i = 0; i < M; ++i) g2 += (i < d) ? (a[2 + i] / m) * (a[2 + i] / m) : 0.0;
             const double r = (g2 > 0.0) ? 1.0 / ::sqrt(g2) : 0.0;
+#pragma unroll
             for (int i = 0; i < M; ++i)
                 out_dir[qg * grad_stride + i] = (i < d && m > 0.0) ? (float)((a[2 + i] / m) * r) : 0.0f;
         }
         if (out_stats) {
             double* st = out_stats + qg * kBatchStats;
             st[0] = se_of(a[0], a[1], n);
+#pragma unroll
             for (int i = 0; i < M; ++i) st[1 + i] = (i < d) ? se_of(a[2 + i], a[2 + M + i], n) : 0.0;
             st[M + 1] = a[2 + 2 * M] / n;
             st[M + 2] = a[3 + 2 * M];
@@ -493,6 +516,7 @@ finalize_batch(const BatchEnv* __restrict__ benv, const double* __restrict__ par
             const double ub = (double)ubar[qg];
             bs += ub * (a[5 + 2 * M] / n);
             bg += ub * (a[6 + 2 * M] / n);
+#pragma unroll
             for (int i = 0; i < kMaxDim; ++i)
                 out_dx[qg * kBatchStride + i] = (i < d) ? (float)(ub * (a[2 + i] / n)) : 0.0f;
         }
