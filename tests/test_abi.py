@@ -196,3 +196,25 @@ def test_varadhan_rejects_bad_arguments(B):
     assert B.lib.wos_varadhan(vp, vp, 4, 9, 9, 1.0, vp, vp, None, None) == B.WOS_EDIM
     assert B.lib.wos_varadhan(vp, vp, 4, 3, 2, 1.0, vp, vp, None, None) == B.WOS_EINVAL
     assert B.lib.wos_varadhan(None, None, 0, 0, 0, 1.0, None, None, None, None) == B.WOS_OK
+
+
+def test_binding_constants_match_the_header(B):
+    """Every integer #define of include/wos.h that the binding also names
+    has the same value there."""
+    src = open(HEADER).read()
+    defs = dict(re.findall(r"^#define\s+(WOS_[A-Z0-9_]+)\s+\(?(-?\d+)u?\)?", src, flags=re.M))
+    shared = [k for k in defs if hasattr(B, k)]
+    assert {"WOS_FP64", "WOS_FULL_SCAN", "WOS_SCALAR_CULL", "WOS_WAVE_SCAN", "WOS_OUT_FP64",
+            "WOS_EINVAL", "WOS_ENOTSUP", "WOS_OUTER_BOX"} <= set(shared)
+    for k in shared:
+        assert int(defs[k]) == getattr(B, k), k
+
+
+def test_option_flags_are_checked_before_device_work(B):
+    """Unknown flag bits are rejected; the read-out, which takes u as given,
+    rejects WOS_OUT_FP64 (it applies to wos_estimate only)."""
+    opt = B.Options(1 << 10, 0, 0, 0)
+    assert B.lib.wos_varadhan(None, None, 0, 2, 2, 1.0, None, None, C.byref(opt), None) == B.WOS_EINVAL
+    assert b"unknown flags" in B.lib.wos_last_error()
+    opt = B.options(out_fp64=True)
+    assert B.lib.wos_varadhan(None, None, 0, 2, 2, 1.0, None, None, C.byref(opt), None) == B.WOS_ENOTSUP
