@@ -36,6 +36,10 @@ if ROOT not in sys.path:
 
 METRIC = "WoS walk-steps/s + ∇u queries/s at fixed std error (d=7), batched vs plain"
 PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector peak (datasheet)
+# one FP32 FMA per lane per cycle: 256 CUs x 4 SIMDs x 16 lanes x 2 FLOP x
+# 2.4 GHz; the datasheet figure counts packed FP32, which these kernels do
+# not use
+PEAK_FP32_UNPACKED_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 KERNEL_SOURCES = ["paper_2406_01713_amd/csrc/wos_device.hpp", "paper_2406_01713_amd/csrc/wos_kernels.hip",
                   "paper_2406_01713_amd/csrc/wos_params.hpp"]
 
@@ -516,6 +520,10 @@ def main():
                         "valu_busy_basis": "share of cycles the vector ALUs issue (SQ_ACTIVE_INST_VALU, "
                                            "rocprofv3 on these kernel sources); achieved/frac count only the "
                                            "distance arithmetic of the executed obstacle tests",
+                        "frac_unpacked": achieved / PEAK_FP32_UNPACKED_TFLOPS,
+                        "unpacked_peak": PEAK_FP32_UNPACKED_TFLOPS,
+                        "unpacked_peak_basis": "256 CUs x 4 SIMDs x 16 lanes x 1 FP32 FMA (2 FLOP) per cycle "
+                                               "x 2.4 GHz; the kernels are built without packed FP32",
                         "kernel": "persistent_kernel<fused fwd+bwd>",
                         "launch_ms": launch_ms,
                         "flops_per_launch": flops,

@@ -171,6 +171,8 @@ def test_fp32_bias_vs_ball_closed_form(B, d):
     u, g, st = gpu_estimate(B, s)
     for q, x in enumerate(pts):
         ue = CF.ball_u(d, sigma, 1.0, x)
+        print(f"d={d} point {q}: u {u[q]:.6f}, exact {ue:.6f}, relative bias {(u[q] - ue) / ue:+.2e}, "
+              f"SE / u {st[q, 0] / ue:.1e}")
         assert abs(u[q] - ue) < 1e-3 * ue, (q, u[q], ue, st[q, 0])
         assert abs(u[q] - ue) <= 4 * st[q, 0] + 2e-4 * ue
         ge = CF.ball_grad(d, sigma, 1.0, x)
@@ -647,6 +649,8 @@ def test_d7_bench_launch_sampled(B, oracle):
         se_u = uw.std(ddof=1) / math.sqrt(len(uw))
         se_g = gw.std(axis=0, ddof=1) / math.sqrt(len(uw))
         r = off[e] + ql
+        print(f"env {e} query {ql}: |u - u_oracle| / SE = {abs(u[r] - uw.mean()) / se_u:.3f}, "
+              f"max |grad - grad_oracle| / SE = {np.max(np.abs(g[r, :7] - gw.mean(0)) / se_g):.3f}")
         assert abs(u[r] - uw.mean()) <= 4 * se_u + 1e-6, (e, ql, u[r], uw.mean(), se_u)
         assert np.all(np.abs(g[r, :7] - gw.mean(0)) <= 4 * se_g + 1e-6), (e, ql)
         assert np.allclose(dx[r, :7], g[r, :7], rtol=1e-6, atol=1e-9), (e, ql)
