@@ -207,7 +207,9 @@ int wos_domain_dim(const wos_domain* dom);
  *             [se_u, se_grad[0..d-1], mean_steps, n_truncated, n_degenerate],
  *             se = sample standard deviation / sqrt(n_walks)
  *   opt       NULL for defaults
- * Plain form: one walk per lane, lanes idle once their walk ends.
+ * Plain form: one walk per lane, lanes idle once their walk ends (about half
+ * the lanes on 7-D workloads); for throughput in FP32 prefer
+ * wos_estimate_batch, also with a single environment, whose lanes refill.
  * FP32 walks keep the weight product's binary exponent apart and sum in FP64,
  * so walks whose weight is below FP32's range still count; a mean below it
  * reads as 0 in FP32 out_u / out_grad (out_stats are FP64) unless WOS_OUT_FP64
