@@ -403,12 +403,13 @@ def test_matrix_core_cull_matches_vector_cull(B):
     assert ma <= mc and ma <= mb
 
 
-def _dense_cloud(seed=21):
-    """d = 3: 1024 spheres (r 0.01-0.02) packed in [-0.5, 0.5]^3 plus 512
-    sparse ones (r 0.05-0.1) in the rest of the box [-3, 3]^3, no goal; g = 1
-    on obstacles.  Queries inside the cloud see every cloud cluster within
-    the outer-box distance, so all 64 walkers of a wave need every cluster of
-    a cloud tile: 1024 pairs per tile, more than the queue takes at once."""
+def _dense_cloud(seed=21, boxes=False):
+    """d = 3: 1024 spheres (r 0.01-0.02) or boxes (half-widths 0.01-0.02)
+    packed in [-0.5, 0.5]^3 plus 512 sparse ones (0.05-0.1) in the rest of
+    the box [-3, 3]^3, no goal; g = 1 on obstacles.  Queries inside the cloud
+    see every cloud cluster within the outer-box distance, so all 64 walkers
+    of a wave need every cluster of a cloud tile: 1024 pairs per tile, more
+    than the queue takes at once."""
     rng = np.random.default_rng(seed)
     d = 3
     dense = rng.uniform(-0.5, 0.5, size=(1024, d))
@@ -420,9 +421,13 @@ def _dense_cloud(seed=21):
     c = np.concatenate([dense, np.array(sparse)])
     r = np.concatenate([rng.uniform(0.01, 0.02, 1024), rng.uniform(0.05, 0.1, 512)])
     s = S._empty(d)
-    s.update(sph_c=c, sph_r=r, d=d, goal_c=None, goal_r=None, outer=S.box_outer(d, 3.0),
+    if boxes:
+        s.update(box_c=c, box_h=np.repeat(r[:, None], d, axis=1) * rng.uniform(0.6, 1.0, size=(len(r), d)))
+    else:
+        s.update(sph_c=c, sph_r=r)
+    s.update(d=d, goal_c=None, goal_r=None, outer=S.box_outer(d, 3.0),
              bdata=S._bdata(0, d, g_goal=0.0, g_obs=1.0, g_outer=0.0), sigma=1.0, eps=1e-3,
-             n_walks=128, seed=seed, name="dense_cloud")
+             n_walks=128, seed=seed, name="dense_box_cloud" if boxes else "dense_cloud")
     qs = []
     while len(qs) < 4:
         p = rng.uniform(-0.4, 0.4, size=d)
@@ -433,15 +438,20 @@ def _dense_cloud(seed=21):
     return s
 
 
-def test_pair_queue_overflow_is_exact(B):
+@pytest.mark.parametrize("boxes", [False, True])
+def test_pair_queue_overflow_is_exact(B, boxes):
     """A tile whose (walker, cluster) pairs overflow the per-wave queue is
     queued row tile by row tile after the waiting pairs are evaluated: walks
     and outputs stay bitwise those of the wave-uniform, vector-ALU and full
-    scans, in the plain, debug-walk and batched launches."""
-    s = _dense_cloud()
+    scans, in the plain, debug-walk and batched launches (sphere and box
+    obstacles)."""
+    s = _dense_cloud(boxes=boxes)
     # precondition: at step 0 the 64 walkers of query 0 need more than
     # 320 - 63 pairs in some tile (they all sit at the query point)
-    cl = B.wos_debug_clusters(3, s["sph_c"], s["sph_r"])["sph"][1]
+    if boxes:
+        cl = B.wos_debug_clusters(3, box_c=s["box_c"], box_h=s["box_h"])["box"][1]
+    else:
+        cl = B.wos_debug_clusters(3, s["sph_c"], s["sph_r"])["sph"][1]
     x0 = s["queries"][0]
     thr = np.min(np.minimum(x0 - s["outer"]["lo"], s["outer"]["hi"] - x0))
     need = np.linalg.norm(cl[:, :3] - x0, axis=1) - cl[:, 3] <= thr
