@@ -36,6 +36,8 @@ if ROOT not in sys.path:
 
 METRIC = "WoS walk-steps/s + ∇u queries/s at fixed std error (d=7), batched vs plain"
 PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector peak (datasheet)
+PEAK_FP32_MFMA_TFLOPS = 157.3  # MI355X dense FP32 matrix-core peak (datasheet)
+JOB_CPU_SHARE = 16
 # one FP32 FMA per lane per cycle: 256 CUs x 4 SIMDs x 16 lanes x 2 FLOP x
 # 2.4 GHz; the datasheet figure counts packed FP32, which these kernels do
 # not use
@@ -66,18 +68,49 @@ def distance_flops_per_step(s):
     return ms * (3 * d + 2) + mb * (5 * d + 1) + 4 * d
 
 
-def executed_distance_flops(s, st):
-    """FP32 operations the distance evaluations of one env's walks actually
-    made, from the work columns of the batched stats (per-walk means of
-    sphere and box distances and cluster bounds evaluated): spheres, bounds
-    (same form as a sphere) and the goal 3d + 2 each, boxes 5d + 1, the outer
-    box 4d per step."""
-    d = s["d"]
+def n_clusters(m):
+    """Clusters of 8 that a domain with m obstacles of one kind keeps (none
+    below 64 obstacles)."""
+    return -(-m // 8) if m >= 64 else 0
+
+
+MFMA_FLOP_PER_PAIR = 24  # 12 features x (multiply + add) per (walker, cluster) pair
+
+
+def executed_flops(s, st):
+    """Distance arithmetic that one env's walks actually executed, from the
+    work columns of the batched stats (per-walk means of sphere and box
+    member distances), split by the unit that runs it:
+      valu  member spheres 3d + 2, member boxes 5d + 1, the goal 3d + 2 and
+            the outer box 4d per walk-step: the vector ALUs;
+      mfma  the cluster test, 16 clusters per matrix-core tile, 12-term dot
+            product per (walker, cluster) pair, for every cluster tile at
+            every walk-step: v_mfma_f32_16x16x4f32 (FP32 matrix cores).
+    Returns (valu, mfma, walk_steps)."""
+    d, n = s["d"], s["n_walks"]
     steps = st[:, 9]
     goal = 1.0 if s.get("goal_r") is not None else 0.0
-    per_walk = ((st[:, 12] + st[:, 14] + goal * steps) * (3 * d + 2) + st[:, 13] * (5 * d + 1)
-                + steps * 4 * d)
-    return float((per_walk * s["n_walks"]).sum())
+    valu = (st[:, 12] * (3 * d + 2) + st[:, 13] * (5 * d + 1) + steps * (goal * (3 * d + 2) + 4 * d)) * n
+    tiles = -(-n_clusters(len(s["sph_r"])) // 16) + -(-n_clusters(len(s["box_h"])) // 16)
+    mfma = steps * n * tiles * 16 * MFMA_FLOP_PER_PAIR
+    return float(valu.sum()), float(mfma.sum()), float((steps * n).sum())
+
+
+def timed(fn, reps, torch, st):
+    """Mean and minimum milliseconds of reps calls of fn (HIP events on the
+    launch stream around each call), after one untimed call."""
+    fn()
+    torch.cuda.synchronize()
+    ms = []
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(st)
+        fn()
+        b.record(st)
+        torch.cuda.synchronize()
+        ms.append(a.elapsed_time(b))
+    return float(np.mean(ms)), float(np.min(ms))
 
 
 def workload():
@@ -117,7 +150,15 @@ def cpu_baseline(envs, budget_walks=400000):
         nq = max(1, int(round(Q * frac * s["n_walks"] / nw)))
         qidx = np.linspace(0, Q - 1, min(nq, Q)).astype(int)
         tasks.append((s, qidx, nw, s["seed"], s.get("env_id", e)))
-    cores = min(os.cpu_count() or 1, 16)
+    # one process per CPU this job may use: the affinity set, at most the 16
+    # CPU threads the GPU host grants a one-GPU job (os.cpu_count() there
+    # counts the whole machine)
+    host_cpus = os.cpu_count() or 1
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = host_cpus
+    cores = max(1, min(usable, JOB_CPU_SHARE))
     # split the largest tasks so all cores stay busy
     chunks = []
     for s, qidx, nw, seed, env in tasks:
@@ -141,7 +182,10 @@ def cpu_baseline(envs, budget_walks=400000):
     return {"value": steps / wall, "unit": "walk-steps/s", "cores": cores, "kind": "oracle",
             "sample": f"{walks} walks ({walks / total:.2e} of the workload: the same walk ids from every "
                       f"environment), FP64 single-threaded oracle x {cores} processes, {wall:.1f} s wall",
-            "cpu": cpu_model}
+            "per_core": steps / wall / cores, "cpu": cpu_model, "host_cpus": host_cpus,
+            "affinity_cpus": usable,
+            "cores_note": f"one process per usable CPU thread, at most {JOB_CPU_SHARE} (the CPU share a "
+                          "one-GPU job gets on the GPU host)"}
 
 
 # ------------------------------------------------------------------ GPU ----
@@ -179,10 +223,16 @@ class Batch:
         self.dg = torch.empty(len(envs), dtype=torch.float64, device=dev)
         self.seed = envs[0]["seed"]
 
-    def run(self, stats=True):
-        self.B.wos_estimate_batch(self.doms, self.q, self.off, self.sig, self.eps, self.nw, self.seed,
-                                  self.u, self.g, self.st if stats else None, self.ubar, self.dx,
-                                  self.ds, self.dg, opt=self.opt)
+    def run(self, stats=True, bwd=True):
+        """One persistent launch: fused forward + backward (u-bar = 1), or the
+        forward pass only."""
+        if bwd:
+            self.B.wos_estimate_batch(self.doms, self.q, self.off, self.sig, self.eps, self.nw, self.seed,
+                                      self.u, self.g, self.st if stats else None, self.ubar, self.dx,
+                                      self.ds, self.dg, opt=self.opt)
+        else:
+            self.B.wos_estimate_batch(self.doms, self.q, self.off, self.sig, self.eps, self.nw, self.seed,
+                                      self.u, self.g, self.st if stats else None, opt=self.opt)
 
 
 class Plain:
@@ -202,17 +252,122 @@ class Plain:
                                   ds=torch.empty(1, dtype=torch.float64, device="cuda"),
                                   dg=torch.empty(1, dtype=torch.float64, device="cuda")))
 
-    def run(self, only=None):
+    def run(self, only=None, fwd=True, bwd=True):
+        """Per env: the forward launch (u, grad u) and / or the backward launch
+        (dx, d sigma, d g_goal: its kernel makes the forward sums too)."""
         B = self.B
         for e, (s, dom, b) in enumerate(zip(self.envs, self.doms, self.bufs)):
             if only is not None and e not in only:
                 continue
             opt = B.options(False, e, 0, full_scan=self.full_scan)
-            B.wos_estimate(dom, b["q"], s["n_walks"], s["sigma"], s["eps"], self.seed, b["u"], b["g"], None,
-                           opt=opt)
-            B.wos_backward(dom, b["q"], s["n_walks"], s["sigma"], s["eps"], self.seed, b["ub"], b["dx"],
-                           b["ds"], b["dg"], None, opt=opt)
+            if fwd:
+                B.wos_estimate(dom, b["q"], s["n_walks"], s["sigma"], s["eps"], self.seed, b["u"], b["g"], None,
+                               opt=opt)
+            if bwd:
+                B.wos_backward(dom, b["q"], s["n_walks"], s["sigma"], s["eps"], self.seed, b["ub"], b["dx"],
+                               b["ds"], b["dg"], None, opt=opt)
         return [b["u"] for b in self.bufs]
+
+
+def max_rel_diff(outs, ub, off):
+    """Largest relative difference of the plain u against the batched u."""
+    diff = 0.0
+    for e, u in enumerate(outs):
+        a = u.cpu().numpy()
+        b = ub[off[e]:off[e + 1]]
+        if len(a):
+            diff = max(diff, float(np.max(np.abs(a - b) / np.maximum(np.abs(a), 1e-6))))
+    return diff
+
+
+def launch_work(envs, off, stats):
+    """(walk-steps, VALU FLOP, MFMA FLOP) of a batched launch's stats."""
+    ws = valu = mfma = 0.0
+    for e, s in enumerate(envs):
+        v, m, w = executed_flops(s, stats[off[e]:off[e + 1]])
+        ws += w
+        valu += v
+        mfma += m
+    return ws, valu, mfma
+
+
+def ragged_c4(B, torch, st, reps=3, plain_reps=2):
+    """The full ragged batch (512 envs, d uniform in 2..7, 16-2048 spheres,
+    1-4096 queries, sigma U[0.5, 8], 2048 walks): one persistent launch,
+    forward only and fused forward + backward (u-bar = 1), against the plain
+    per-env launches (one walk per lane, no refill) on the same walks."""
+    from paper_2406_01713_amd import scenes as S
+    t = time.perf_counter()
+    envs = S.scene_c4()
+    draw_s = time.perf_counter() - t
+    bat = Batch(B, envs, torch)
+    fwd_ms, fwd_min = timed(lambda: bat.run(bwd=False), reps, torch, st)
+    ws_f, valu_f, mfma_f = launch_work(envs, bat.off, bat.st.cpu().numpy())
+    fused_ms, fused_min = timed(lambda: bat.run(), reps, torch, st)
+    stats = bat.st.cpu().numpy()
+    ws, valu, mfma = launch_work(envs, bat.off, stats)
+    by_d = {}
+    for d in range(2, 8):
+        es = [e for e, s in enumerate(envs) if s["d"] == d]
+        by_d[str(d)] = {"envs": len(es), "queries": int(sum(len(envs[e]["queries"]) for e in es)),
+                        "walk_steps": float(sum(executed_flops(envs[e], stats[bat.off[e]:bat.off[e + 1]])[2]
+                                                for e in es))}
+    pl = Plain(B, envs, bat.doms, torch, bat.seed)
+    pf_ms, _ = timed(lambda: pl.run(bwd=False), plain_reps, torch, st)
+    pb_ms, _ = timed(lambda: pl.run(fwd=False), plain_reps, torch, st)
+    diff = max_rel_diff(pl.run(bwd=False), bat.u.cpu().numpy(), bat.off)
+    torch.cuda.synchronize()
+    res = {"workload": "512 envs, d U{2..7}, 16-2048 spheres r U[0.05, 0.4], 1-4096 queries, sigma U[0.5, 8], "
+                       "eps 1e-4, 2048 walks; one persistent launch",
+           "envs": len(envs), "queries": int(bat.off[-1]), "walks": int(bat.off[-1]) * 2048,
+           "walk_steps_per_step": ws, "by_d": by_d, "draw_s": draw_s, "repeats": reps,
+           "forward": {"ms": fwd_ms, "ms_min": fwd_min, "walk_steps_per_s": ws_f / (fwd_ms / 1e3),
+                       "valu_tflops": valu_f / (fwd_ms / 1e3) / 1e12, "mfma_tflops": mfma_f / (fwd_ms / 1e3) / 1e12},
+           "fused_fwd_bwd": {"ms": fused_ms, "ms_min": fused_min, "walk_steps_per_s": ws / (fused_ms / 1e3),
+                             "valu_tflops": valu / (fused_ms / 1e3) / 1e12,
+                             "mfma_tflops": mfma / (fused_ms / 1e3) / 1e12},
+           "plain": {"forward_ms": pf_ms, "backward_ms": pb_ms, "launches_per_pass": len(envs),
+                     "forward_walk_steps_per_s": ws_f / (pf_ms / 1e3),
+                     "fwd_plus_bwd_walk_steps_per_s": ws / ((pf_ms + pb_ms) / 1e3),
+                     "repeats": plain_reps, "max_rel_diff_u_vs_batched": diff},
+           "batched_vs_plain_forward": pf_ms / fwd_ms,
+           "batched_vs_plain_fwd_plus_bwd": (pf_ms + pb_ms) / fused_ms,
+           "batched_vs_plain_like_for_like": pb_ms / fused_ms}
+    del pl, bat
+    return res
+
+
+def c2_forward(B, torch, st, reps=3):
+    """The 6-D forward configuration: 4096 uniform free queries x 4096 walks,
+    256 spheres, sigma = 4, eps = 1e-4, FP32 u and grad u; the plain launch
+    and the persistent launch of the one environment."""
+    from paper_2406_01713_amd import scenes as S
+    s = S.scene_c2()
+    dom = B.Domain(s)
+    q = torch.as_tensor(s["queries"], dtype=torch.float32, device="cuda")
+    Q, d = q.shape
+    u = torch.empty(Q, device="cuda")
+    g = torch.empty(Q, d, device="cuda")
+    sto = torch.empty(Q, d + 4, dtype=torch.float64, device="cuda")
+
+    def plain():
+        B.wos_estimate(dom, q, s["n_walks"], s["sigma"], s["eps"], s["seed"], u, g, sto)
+
+    p_ms, p_min = timed(plain, reps, torch, st)
+    ws_plain = float((sto.cpu().numpy()[:, d + 1] * s["n_walks"]).sum())
+    bat = Batch(B, [s], torch)
+    b_ms, b_min = timed(lambda: bat.run(bwd=False), reps, torch, st)
+    ws, valu, mfma = launch_work([s], bat.off, bat.st.cpu().numpy())
+    assert abs(ws - ws_plain) <= 1e-9 * ws, (ws, ws_plain)  # the same walks
+    res = {"workload": "d6: 4096 uniform free queries x 4096 walks, 256 spheres r U[0.1, 0.4], sigma 4, eps 1e-4, "
+                       "FP32 forward u and grad u", "walk_steps_per_step": ws, "repeats": reps,
+           "plain": {"ms": p_ms, "ms_min": p_min, "walk_steps_per_s": ws / (p_ms / 1e3)},
+           "batched": {"ms": b_ms, "ms_min": b_min, "walk_steps_per_s": ws / (b_ms / 1e3),
+                       "valu_tflops": valu / (b_ms / 1e3) / 1e12, "mfma_tflops": mfma / (b_ms / 1e3) / 1e12},
+           "grad_queries_per_s": Q / (b_ms / 1e3),
+           "max_rel_diff_u_vs_batched": max_rel_diff([u], bat.u.cpu().numpy(), bat.off)}
+    del bat
+    return res
 
 
 def counter_entry(khash):
@@ -233,14 +388,7 @@ def counter_entry(khash):
 def near_goal_starts(s, n, seed=5):
     """Clear starts 0.05-0.5 outside the goal sphere (random directions)."""
     from paper_2406_01713_amd import scenes as S
-    rng = np.random.default_rng(seed)
-    out = []
-    while len(out) < n:
-        v = rng.normal(size=s["d"])
-        p = s["goal_c"] + (s["goal_r"] + rng.uniform(0.05, 0.5)) * v / np.linalg.norm(v)
-        if S.is_clear(p, s, 0.02):
-            out.append(p)
-    return np.array(out)
+    return S.near_goal_points(s, n, gap_lo=0.05, gap_hi=0.5, seed=seed, delta=0.02)
 
 
 def planning(B, torch, n_steps, near_goal=False, source=False):
@@ -409,6 +557,8 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--plain-reps", type=int, default=3, help="timed repeats of the plain per-env path")
+    ap.add_argument("--no-c4", action="store_true", help="skip the full ragged batch and the 6-D forward set")
     ap.add_argument("--full-scan", action="store_true",
                     help="scan every obstacle each step (no cluster culling): same results, more work")
     ap.add_argument("--no-cpu", action="store_true")
@@ -429,6 +579,7 @@ def main():
         sys.exit(2)
     if args.only_batched:
         args.no_plain = args.no_cpu = args.no_plan = args.no_se = args.no_source = args.no_eval_env = True
+        args.no_c4 = True
 
     t = time.perf_counter()
     envs = workload()
@@ -477,17 +628,12 @@ def main():
     log(f"batched fused fwd+bwd: {ms_step:.1f} ms/step")
 
     stats = bat.st.cpu().numpy()
-    walk_steps = 0.0
-    flops = 0.0
-    flops_full = 0.0
-    for e, s in enumerate(envs):
-        sl = slice(bat.off[e], bat.off[e + 1])
-        ws = float((stats[sl, 9] * s["n_walks"]).sum())
-        walk_steps += ws
-        flops_full += ws * distance_flops_per_step(s)
-        flops += executed_distance_flops(s, stats[sl])
+    walk_steps, valu, mfma = launch_work(envs, bat.off, stats)
+    flops_full = sum(float((stats[bat.off[e]:bat.off[e + 1], 9] * s["n_walks"]).sum()) * distance_flops_per_step(s)
+                     for e, s in enumerate(envs))
     value = walk_steps / (ms_step / 1e3)
-    achieved = flops / (launch_ms / 1e3) / 1e12
+    valu_rate = valu / (launch_ms / 1e3) / 1e12
+    mfma_rate = mfma / (launch_ms / 1e3) / 1e12
     khash = kernel_hash()
     counters = counter_entry(khash)
     ceilings = {}
@@ -513,54 +659,66 @@ def main():
                       "walk_steps_per_step": walk_steps, "eps": 1e-4, "seed": int(bat.seed),
                       "obstacle_scan": "every obstacle" if args.full_scan else
                                        "cluster-culled (exact: same walks as a full scan)"},
-           "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
-                        "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
+           "roofline": {"bound": "alu", "achieved": valu_rate, "peak": PEAK_FP32_TFLOPS,
+                        "unit": "TFLOP/s", "frac": valu_rate / PEAK_FP32_TFLOPS,
                         "traffic": counters.get("bytes_per_launch"),
+                        "basis": "distance arithmetic executed on the vector ALUs: member sphere (3d + 2) and "
+                                 "box (5d + 1) distances, the goal (3d + 2) and the outer box (4d) per walk-step, "
+                                 "counted by the kernel's work tallies; the cluster test runs on the matrix "
+                                 "cores and is reported under 'mfma'",
+                        "mfma": {"achieved": mfma_rate, "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
+                                 "frac": mfma_rate / PEAK_FP32_MFMA_TFLOPS, "flops_per_launch": mfma,
+                                 "basis": "cluster tests (12-term dot product, 24 FLOP per walker and cluster) "
+                                          "for every 16-cluster tile at every walk-step, "
+                                          "v_mfma_f32_16x16x4f32; peak = MI355X dense FP32 matrix peak"},
                         "valu_busy": counters.get("valu_busy"),
                         "valu_busy_basis": "share of cycles the vector ALUs issue (SQ_ACTIVE_INST_VALU, "
-                                           "rocprofv3 on these kernel sources); achieved/frac count only the "
-                                           "distance arithmetic of the executed obstacle tests",
-                        "frac_unpacked": achieved / PEAK_FP32_UNPACKED_TFLOPS,
+                                           "rocprofv3 on these kernel sources)",
+                        "frac_unpacked": valu_rate / PEAK_FP32_UNPACKED_TFLOPS,
                         "unpacked_peak": PEAK_FP32_UNPACKED_TFLOPS,
                         "unpacked_peak_basis": "256 CUs x 4 SIMDs x 16 lanes x 1 FP32 FMA (2 FLOP) per cycle "
                                                "x 2.4 GHz; the kernels are built without packed FP32",
                         "kernel": "persistent_kernel<fused fwd+bwd>",
                         "launch_ms": launch_ms,
-                        "flops_per_launch": flops,
-                        "flops_basis": "distance operations executed (evaluated obstacles and cluster "
-                                       "bounds, counted by the kernel); a scan of every obstacle would "
-                                       "need full_scan_flops_per_launch",
+                        "valu_flops_per_launch": valu,
                         "full_scan_flops_per_launch": flops_full,
-                        "work_fraction": flops / flops_full,
+                        "work_fraction": valu / flops_full,
+                        "work_fraction_basis": "VALU distance FLOP executed / the FLOP of a scan of every "
+                                               "obstacle at every walk-step (exact culling: same walks)",
                         "peak_basis": "MI355X FP32 vector peak, 157.3 TFLOP/s (datasheet); measured ceilings "
                                       "of this code's instruction types in 'measured'",
                         "measured": ceilings,
-                        "frac_of_measured_sphere_loop": (achieved / ceilings["sphere_loop_d7_tflops"]
-                                                         if ceilings else None),
                         "kernel_hash": khash}}
 
     if not args.no_plain:
         t = time.perf_counter()
         pl = Plain(B, envs, bat.doms, torch, bat.seed, full_scan=args.full_scan)
-        pl.run(only={len(envs) - 1})  # loads the plain kernels
-        torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(st)
-        outs = pl.run()
-        e1.record(st)
-        torch.cuda.synchronize()
-        plain_ms = e0.elapsed_time(e1)
-        ub = bat.u.cpu().numpy()
-        diff = 0.0
-        for e, u in enumerate(outs):
-            a = u.cpu().numpy()
-            b = ub[bat.off[e]:bat.off[e + 1]]
-            diff = max(diff, float(np.max(np.abs(a - b) / np.maximum(np.abs(a), 1e-6))) if len(a) else 0.0)
-        out["plain"] = {"ms_per_step": plain_ms, "walk_steps_per_s": walk_steps / (plain_ms / 1e3),
-                        "launches": 2 * len(envs), "max_rel_diff_u_vs_batched": diff}
+        plain_ms, plain_min = timed(lambda: pl.run(), args.plain_reps, torch, st)
+        bwd_ms, bwd_min = timed(lambda: pl.run(fwd=False), args.plain_reps, torch, st)
+        diff = max_rel_diff(pl.run(bwd=False), bat.u.cpu().numpy(), bat.off)
+        out["plain"] = {"ms_per_step": plain_ms, "ms_min": plain_min, "repeats": args.plain_reps,
+                        "walk_steps_per_s": walk_steps / (plain_ms / 1e3), "launches": 2 * len(envs),
+                        "backward_only_ms": bwd_ms, "backward_only_ms_min": bwd_min,
+                        "max_rel_diff_u_vs_batched": diff,
+                        "note": "plain = a forward launch and a backward launch per env, one walk per lane; "
+                                "the backward kernel alone makes the sums of the fused launch (u, grad u, "
+                                "d sigma, d g_goal), so backward_only is the like-for-like comparison"}
         out["batched_vs_plain"] = plain_ms / ms_step
-        log(f"plain fwd+bwd per env: {plain_ms:.1f} ms, batched speed-up {plain_ms / ms_step:.2f}x "
+        out["batched_vs_plain_like_for_like"] = bwd_ms / ms_step
+        log(f"plain fwd+bwd per env: {plain_ms:.1f} ms (backward alone {bwd_ms:.1f} ms), batched speed-up "
+            f"{plain_ms / ms_step:.2f}x, like for like {bwd_ms / ms_step:.2f}x ({time.perf_counter() - t:.1f} s)")
+
+    if not args.no_c4:
+        t = time.perf_counter()
+        out["ragged_c4"] = ragged_c4(B, torch, st)
+        r = out["ragged_c4"]
+        log(f"ragged C4: fused {r['fused_fwd_bwd']['ms']:.1f} ms ({r['fused_fwd_bwd']['walk_steps_per_s']:.3e} "
+            f"walk-steps/s), forward {r['forward']['ms']:.1f} ms; plain fwd {r['plain']['forward_ms']:.1f} ms, "
+            f"bwd {r['plain']['backward_ms']:.1f} ms ({time.perf_counter() - t:.1f} s)")
+        t = time.perf_counter()
+        out["c2_d6_forward"] = c2_forward(B, torch, st)
+        r = out["c2_d6_forward"]
+        log(f"C2 d6 forward: plain {r['plain']['ms']:.1f} ms, batched {r['batched']['ms']:.1f} ms "
             f"({time.perf_counter() - t:.1f} s)")
 
     if not args.no_se:

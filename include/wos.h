@@ -130,7 +130,7 @@ typedef struct {
     double b;            /* affine offset */
 } wos_bdata;
 
-/* Planar serial arm with revolute joints (Sec. V-B): the walk coordinates are
+/* Planar serial arm with revolute joints (Sec. V-A): the walk coordinates are
  * the d joint angles, link i (length l_i) points along q_1 + ... + q_i in the
  * task plane, and the base joint sits at the plane's origin.  Obstacle points
  * in the task plane make the configurations that put a link on a point the

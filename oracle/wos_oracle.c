@@ -39,7 +39,7 @@
  *       grad_hat u(x_0) = (d / R_0) C1(R_0) u_hat(x_1) v_0
  *                         + c_imp amp grad_x G_B(x_0, z) 1{|z - x_0| < R_0},
  *   with u_hat(x_1) the same sum over the walk from x_1 (weights W1_k).
- *   Planar arm (Sec. V-B): with joint coordinates q and task-space obstacle
+ *   Planar arm (Sec. V-A): with joint coordinates q and task-space obstacle
  *   points, the joint-space distance to collision is replaced by the lower
  *   bound d_tau(q) / K, d_tau the planar distance between the points and the
  *   arm's links and K a Lipschitz constant of the planar forward kinematics
@@ -215,7 +215,7 @@ static double dist_outer(const or_domain* D, const double* x)
     return D->outer_r - sqrt(s);
 }
 
-/* Lipschitz constant of the planar forward kinematics (Sec. V-B): joint n
+/* Lipschitz constant of the planar forward kinematics (Sec. V-A): joint n
  * moves every point beyond it at most (l_n + ... + l_N) per radian, so the
  * Jacobian of any point of the arm has Frobenius norm at most
  * K = sqrt(sum_n (l_n + ... + l_N)^2).  (The printed sum runs over the first

@@ -8,6 +8,9 @@ differentiable (its cotangent is ignored).
 """
 from __future__ import annotations
 
+import hashlib
+
+import numpy as np
 import torch
 
 from . import binding as B
@@ -25,8 +28,28 @@ class WoSFunction(torch.autograd.Function):
     _cache = {}
 
     @staticmethod
+    def _digest(obj, h):
+        """Feed the scene's contents (arrays by value, nested dicts in key
+        order) into the hash h."""
+        if isinstance(obj, dict):
+            for k in sorted(obj):
+                h.update(repr(k).encode())
+                WoSFunction._digest(obj[k], h)
+        elif isinstance(obj, (np.ndarray, list, tuple)):
+            a = np.ascontiguousarray(np.asarray(obj, dtype=np.float64))
+            h.update(repr(a.shape).encode())
+            h.update(a.tobytes())
+        else:
+            h.update(repr(obj).encode())
+
+    @staticmethod
     def _domain(scene, g_goal):
-        key = (id(scene), float(g_goal))
+        """The device domain of (scene, g_goal), cached by the scene's contents:
+        a scene changed in place, or a new scene at a recycled address, gets
+        its own domain."""
+        h = hashlib.sha256()
+        WoSFunction._digest({k: v for k, v in scene.items() if k != "queries"}, h)
+        key = (h.hexdigest(), float(g_goal))
         dom = WoSFunction._cache.get(key)
         if dom is None:
             sc = dict(scene)

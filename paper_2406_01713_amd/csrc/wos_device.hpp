@@ -420,7 +420,7 @@ __device__ __forceinline__ float cluster_min_mfma(cptr<float> rows, const float*
     return best;
 }
 
-// Planar arm (Sec. V-B): the task-plane distance between the obstacle points
+// Planar arm (Sec. V-A): the task-plane distance between the obstacle points
 // and the links at joint angles x (link i turns by x_0 + ... + x_i, base joint
 // at the origin), times 1 / K, a lower bound of the joint-space distance to
 // collision.

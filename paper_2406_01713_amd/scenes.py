@@ -264,6 +264,34 @@ def scene_c4(n_envs=512, n_walks=2048, seed=0, dims=None, q_cap=None):
     return envs
 
 
+def scene_spheres(d, m_sph=256, n_queries=16, n_walks=1024, sigma=2.0, eps=1e-4, seed=0,
+                  scene_seed=None):
+    """A sphere-cluttered box [-pi, pi]^d of any dimension 2..8 in the form
+    of the 6-D and 7-D workloads: m_sph spheres r U[0.1, 0.4], goal r = 0.15,
+    uniform free queries drawn after the obstacles.  scene_seed (default d)
+    keys the generator."""
+    s, rng = _cluttered(d, m_sph, 0, d if scene_seed is None else scene_seed)
+    s.update(sigma=float(sigma), eps=float(eps), queries=_free_points(rng, s, n_queries),
+             n_walks=n_walks, seed=seed, name=f"spheres_d{d}_m{m_sph}")
+    return s
+
+
+def near_goal_points(scene, n, gap_lo=0.02, gap_hi=0.1, seed=5, delta=0.01):
+    """n points at a distance U[gap_lo, gap_hi] outside the goal sphere in
+    uniformly random directions, each clear of the obstacles and the outer
+    boundary by delta (redrawn otherwise): queries whose walks reach the
+    goal often, also in 6 and 7 dimensions."""
+    rng = np.random.default_rng(seed)
+    d = scene["d"]
+    out = []
+    while len(out) < n:
+        v = rng.normal(size=d)
+        p = scene["goal_c"] + (scene["goal_r"] + rng.uniform(gap_lo, gap_hi)) * v / np.sqrt((v ** 2).sum())
+        if is_clear(p, scene, delta):
+            out.append(p)
+    return np.array(out)
+
+
 def scene_c5(n_starts=256, n_walks=2048, seed=0):
     """Planning in d = 7: 512 spheres r U[0.1, 0.4] + 512 axis-aligned boxes
     (half-widths U[0.05, 0.3] per axis), sigma = 2, eps = 1e-4, goal r = 0.15,

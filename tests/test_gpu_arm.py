@@ -1,4 +1,4 @@
-"""GPU parity of the planar-arm distance bound (Sec. V-B) and the RR task of
+"""GPU parity of the planar-arm distance bound (Sec. V-A) and the RR task of
 Sec. VII against the FP64 oracle on identical Philox streams: per-walk
 records with the Lipschitz bound (RR and longer arms), FP32 means within
 4 SE, batched vs plain, and the RR planning task with the IK-point and

@@ -1,4 +1,4 @@
-"""Pins of the oracle's planar-arm distance (Sec. V-B: the joint-space
+"""Pins of the oracle's planar-arm distance (Sec. V-A: the joint-space
 distance to collision bounded below by the task-space distance over a
 Lipschitz constant of the forward kinematics) and of the IK-based collision
 points of the RR task (Sec. VII), on the CPU.  Forward kinematics here is
@@ -94,7 +94,7 @@ def test_K_bounds_every_arm_point_speed(oracle, links, pts):
 
 @pytest.mark.parametrize("links,pts", ARMS)
 def test_safe_ball_holds_no_collision(oracle, links, pts):
-    """Sec. V-B, eq. safe_ball: every configuration in B(q, d_tau(q) / K)
+    """Sec. V, eq. safe_ball: every configuration in B(q, d_tau(q) / K)
     keeps the arm off every obstacle point."""
     s = arm_scene(links, pts)
     dom = oracle.Domain(s)
