@@ -202,6 +202,53 @@ def test_standard_error_decays_as_inverse_sqrt_n(oracle):
     assert -0.55 <= slope <= -0.45, slope
 
 
+def _se_scale_case(name):
+    if name == "c1":  # the three clear grid points nearest the goal (signal on many walks)
+        s = S.scene_c1()
+        free = [i for i, x in enumerate(s["queries"]) if S.is_clear(x, s, 0.05)]
+        near = sorted(free, key=lambda i: np.linalg.norm(s["queries"][i] - s["goal_c"]))[:3]
+        s["queries"] = s["queries"][near]
+    elif name == "ball3":
+        s = S.scene_ball(3, R=1.0, sigma=2.0, eps=1e-4, queries=[[0.5, 0.0, 0.0], [0.1, -0.6, 0.3]])
+    else:  # plane-wave data in a 5-D ball: u = exp(k.x), a gradient in every coordinate
+        k = S.plane_wave_k(5, 2.0, seed=3)
+        s = S.scene_ball(5, R=1.0, sigma=2.0, eps=1e-4, queries=[[0.3, -0.2, 0.1, 0.0, 0.4]], mode=2, ak=k)
+    return s
+
+
+@pytest.mark.parametrize("name", ["c1", "ball3", "plane_d5"])
+def test_standard_error_scale_matches_spread_of_estimates(oracle, name):
+    """Sec. IV-B: the reported standard error is the standard deviation of the
+    mean of n walks.  K = 256 independent estimates (distinct seeds, n = 256
+    walks each): the empirical standard deviation of their values must agree
+    with the root mean square of their reported SEs (SE^2 is unbiased for
+    sigma^2 / n; SE itself is biased low for skewed walk values), for u and
+    every gradient component.  The estimates are near-normal means, so
+    (K - 1) s^2 / sigma^2 is chi-square with K - 1 degrees of freedom
+    (relative spread of s about 1 / sqrt(2 (K - 1)) = 4.4 %); the mean of the
+    K squared SEs adds its own spread.  The bar is 4 of the combined
+    relative spreads (about 20 %): a constant-factor error of 1.5 in the SE
+    fails it."""
+    s = _se_scale_case(name)
+    d = s["d"]
+    K, n = 256, 256
+    vals, ses = [], []
+    for k in range(K):
+        u, g, st_ = oracle.estimate(s, n_walks=n, seed=1000 + k)
+        vals.append(np.concatenate([u[:, None], g], axis=1))
+        ses.append(st_[:, :1 + d])
+    vals, ses = np.array(vals), np.array(ses)  # (K, Q, 1 + d)
+    emp = vals.std(axis=0, ddof=1)
+    se2 = ses ** 2
+    rep = np.sqrt(se2.mean(axis=0))
+    spread = np.sqrt(1.0 / (2 * (K - 1)) + 0.25 * se2.var(axis=0, ddof=1) / (K * rep ** 4))
+    ratio = emp / rep
+    print(f"{name}: empirical sd / rms reported SE per (query, component):\n{np.round(ratio, 3)}\n"
+          f"bars: {np.round(4 * spread, 3)}")
+    assert np.all(rep > 0)
+    assert np.all(np.abs(ratio - 1.0) <= 4 * spread), (ratio, spread)
+
+
 # ------------------------------------------------------------- invariants ----
 
 def _random_scene(d, seed, sigma):
