@@ -282,6 +282,39 @@ int wos_estimate_batch(const wos_domain* const* envs, int n_envs, const float* q
                        void* stream);
 
 /*
+ * wos_estimate_batch_noalloc -- wos_estimate_batch for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): same arguments, kernels, walks and
+ * results, but its tables, work-unit counter and partial sums live in a
+ * fixed device array of WOS_NOALLOC_SCRATCH_BYTES per device, reserved when
+ * the library's device code loads on that device and held until the process
+ * ends.  The call makes no device or pinned-host allocation; it copies
+ * about (sizeof env table) x n_envs bytes from static host staging and clears
+ * the counter with a fill kernel.
+ * Limits: at most WOS_NOALLOC_MAX_ENVS environments, and 256-byte-aligned
+ * [counter | tables | 200 bytes per work unit] within the array; a work unit
+ * is one (query, walk range), so a batch needs about 200 bytes per query
+ * when its queries take a few thousand walks (the full 512-env ragged batch,
+ * 266081 queries x 2048 walks, needs 54 MB).  A batch beyond either limit
+ * returns WOS_EINVAL before anything is launched.
+ * Concurrency: every call on a device uses that device's one array, which
+ * keeps the last call's contents.  Host threads are serialised by the
+ * library, but calls whose work overlaps on the device (different streams
+ * without ordering between them) race on the array: order them on one
+ * stream or synchronise between them.
+ * Errors: as wos_estimate_batch; WOS_EINVAL for a batch beyond the limits;
+ * WOS_EHIP if the array's address cannot be resolved on the device.
+ */
+#define WOS_NOALLOC_SCRATCH_BYTES 67108864u /* 64 MiB */
+#define WOS_NOALLOC_MAX_ENVS 1024
+int wos_estimate_batch_noalloc(const wos_domain* const* envs, int n_envs, const float* queries,
+                               const int64_t* q_offsets, const double* sigma, const double* eps,
+                               const int64_t* n_walks, uint64_t seed, float* out_u, float* out_grad,
+                               double* out_stats, const float* grad_u, float* out_dx,
+                               double* out_dsigma, double* out_dg, const wos_options* opt,
+                               void* stream);
+
+/*
  * wos_plan_create -- gradient-ascent planning loop (Sec. III, screened-harmonic
  * paths; Sec. VII step rule s = min(s_ub, d(x)/2)) captured once as a HIP graph
  * of [fused forward + backward walk kernel, finalize, update] on `stream`.

@@ -20,6 +20,8 @@ LIB_PATH = os.path.join(PKG, "libwos.so")
 WOS_OK, WOS_EINVAL, WOS_EDIM, WOS_ENOMEM, WOS_EHIP, WOS_ENOTSUP = 0, -1, -2, -3, -4, -5
 WOS_FP32, WOS_FP64, WOS_FULL_SCAN, WOS_SCALAR_CULL, WOS_WAVE_SCAN = 0, 1, 2, 4, 8
 WOS_OUT_FP64 = 16
+WOS_NOALLOC_SCRATCH_BYTES = 64 << 20
+WOS_NOALLOC_MAX_ENVS = 1024
 CLUSTER = 8
 BATCH_STATS = 15
 WOS_OUTER_BOX, WOS_OUTER_BALL = 0, 1
@@ -27,7 +29,7 @@ BATCH_STRIDE = 8
 MAX_DIM = 8
 
 EXPORTED = ["wos_create_domain", "wos_destroy_domain", "wos_domain_dim", "wos_estimate",
-            "wos_backward", "wos_estimate_batch", "wos_plan_create", "wos_plan_step",
+            "wos_backward", "wos_estimate_batch", "wos_estimate_batch_noalloc", "wos_plan_create", "wos_plan_step",
             "wos_plan_buffers", "wos_plan_read", "wos_plan_destroy", "wos_autotune", "wos_set_autotune_cache",
             "wos_debug_walks", "wos_debug_clusters", "wos_varadhan", "wos_microbench", "wos_last_error"]
 
@@ -92,6 +94,7 @@ def _load():
                                C.POINTER(Options), vp]
     L.wos_estimate_batch.argtypes = [C.POINTER(vp), C.c_int, vp, C.POINTER(i64), dp, dp, C.POINTER(i64), u64,
                                      vp, vp, vp, vp, vp, vp, vp, C.POINTER(Options), vp]
+    L.wos_estimate_batch_noalloc.argtypes = L.wos_estimate_batch.argtypes
     L.wos_plan_create.argtypes = [vp, vp, i64, i64, C.c_double, C.c_double, C.c_double, u64,
                                   C.POINTER(Options), vp, C.POINTER(vp)]
     L.wos_plan_step.argtypes = [vp, C.c_int]
@@ -240,19 +243,20 @@ def wos_backward(dom, queries, n_walks, sigma, eps, seed, grad_u, out_dx, out_ds
 
 def wos_estimate_batch(doms, queries, q_offsets, sigma, eps, n_walks, seed, out_u, out_grad=None,
                        out_stats=None, grad_u=None, out_dx=None, out_dsigma=None, out_dg=None,
-                       opt=None, stream=None):
+                       opt=None, stream=None, noalloc=False):
+    """The batched call; noalloc=True calls wos_estimate_batch_noalloc (the
+    same launch with the library's fixed per-device scratch array)."""
     n = len(doms)
+    fn = lib.wos_estimate_batch_noalloc if noalloc else lib.wos_estimate_batch
     hs = (C.c_void_p * n)(*[dm.handle.value for dm in doms])
     qo = np.ascontiguousarray(np.asarray(q_offsets, dtype=np.int64))
     sg = _f64(sigma)
     ep = _f64(eps)
     nw = np.ascontiguousarray(np.broadcast_to(np.asarray(n_walks, dtype=np.int64), (n,)))
-    check(lib.wos_estimate_batch(hs, n, _ptr(queries), qo.ctypes.data_as(C.POINTER(C.c_int64)),
-                                 _dp(sg), _dp(ep), nw.ctypes.data_as(C.POINTER(C.c_int64)), int(seed),
-                                 _ptr(out_u),
-                                 _ptr(out_grad), _ptr(out_stats), _ptr(grad_u), _ptr(out_dx),
-                                 _ptr(out_dsigma), _ptr(out_dg),
-                                 C.byref(opt) if opt is not None else None, _stream(stream)))
+    check(fn(hs, n, _ptr(queries), qo.ctypes.data_as(C.POINTER(C.c_int64)),
+             _dp(sg), _dp(ep), nw.ctypes.data_as(C.POINTER(C.c_int64)), int(seed),
+             _ptr(out_u), _ptr(out_grad), _ptr(out_stats), _ptr(grad_u), _ptr(out_dx),
+             _ptr(out_dsigma), _ptr(out_dg), C.byref(opt) if opt is not None else None, _stream(stream)))
 
 
 def wos_debug_walks(dom, query, q_index, w0, n, sigma, eps, seed, opt=None):

@@ -648,16 +648,19 @@ double unit_cost(const wos_domain* D, int64_t wps)
 }
 
 struct BatchLayout {
-    std::vector<BatchEnv> benv;
     int64_t total_units = 0;
     int grid = 0;
 };
 
 // Work units: each query's walks are split into `splits` ranges so that the
 // launch has about units_per_wave units per resident wave; envs are ordered
-// by decreasing unit cost (longest-processing-time first).
+// by decreasing unit cost (longest-processing-time first, ties in caller
+// order).  order (n_envs ints) is working storage; benv receives the
+// n_envs rows of the unit table.  force: launch-shape fields > 0 override
+// the tuned ones.
 void plan_batch(const wos_domain* const* envs, const int64_t* q_off, int n_envs, const int64_t* n_walks,
-                int q_stride, int force_upw, int force_gm, int force_wpl, bool full_scan, bool src, BatchLayout& L)
+                int q_stride, const Tune* force, bool full_scan, bool src, int* order, BatchEnv* benv,
+                BatchLayout& L)
 {
     const int block = 256;
     int64_t sumQW = 0, maxM = 0, heavyQ = 0, maxW = 1;
@@ -676,9 +679,9 @@ void plan_batch(const wos_domain* const* envs, const int64_t* q_off, int n_envs,
         }
     }
     Tune t = lookup_tune(heavy_d, maxM, heavyQ);
-    if (force_upw > 0) t.units_per_wave = force_upw;
-    if (force_gm > 0) t.grid_mult = force_gm;
-    if (force_wpl > 0) t.walks_per_lane = force_wpl;
+    if (force && force->units_per_wave > 0) t.units_per_wave = force->units_per_wave;
+    if (force && force->grid_mult > 0) t.grid_mult = force->grid_mult;
+    if (force && force->walks_per_lane > 0) t.walks_per_lane = force->walks_per_lane;
     const int resident_blocks = persistent_resident_blocks(true, src, block);
     L.grid = std::max(1, resident_blocks * t.grid_mult);
     const int64_t waves = (int64_t)L.grid * (block / kWave);
@@ -694,19 +697,21 @@ void plan_batch(const wos_domain* const* envs, const int64_t* q_off, int n_envs,
     wps = std::min(wps, maxW);
     wps = ((wps + kWave - 1) / kWave) * kWave;
 
-    std::vector<int> order(n_envs);
-    for (int e = 0; e < n_envs; ++e) order[e] = e;
     auto env_wps = [&](int e) { return std::min<int64_t>(wps, ((n_walks[e] + kWave - 1) / kWave) * kWave); };
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-        const int64_t qa = q_off[a + 1] - q_off[a], qb = q_off[b + 1] - q_off[b];
-        const double ca = qa ? unit_cost(envs[a], env_wps(a)) : -1.0, cb = qb ? unit_cost(envs[b], env_wps(b)) : -1.0;
-        return ca > cb;
+    auto cost = [&](int e) {
+        return q_off[e + 1] > q_off[e] ? unit_cost(envs[e], env_wps(e)) : -1.0;
+    };
+    for (int e = 0; e < n_envs; ++e) order[e] = e;
+    // std::sort with the caller index as tie-break: the order of a stable
+    // sort, without the temporary buffer std::stable_sort allocates
+    std::sort(order, order + n_envs, [&](int a, int b) {
+        const double ca = cost(a), cb = cost(b);
+        return ca > cb || (ca == cb && a < b);
     });
-    L.benv.resize(n_envs);
     int64_t uoff = 0;
     for (int i = 0; i < n_envs; ++i) {
         const int e = order[i];
-        BatchEnv& b = L.benv[i];
+        BatchEnv& b = benv[i];
         const int64_t w = env_wps(e);
         const int64_t splits = (n_walks[e] + w - 1) / w;
         b.q_off = q_off[e];
@@ -725,11 +730,64 @@ void plan_batch(const wos_domain* const* envs, const int64_t* q_off, int n_envs,
     L.total_units = uoff;
 }
 
+}  // namespace
+
+// ----------------------------------------------------------------------------
+// Scratch of wos_estimate_batch_noalloc: one array per device, reserved when
+// the library's device code loads there and held until the process ends.  In
+// host code its name is only a stand-in: the device address comes from
+// hipGetSymbolAddress, resolved once per device with that device current.
+// Layout per call: [work-unit counter | env and unit tables | partial sums],
+// each part 256-byte aligned.
+// ----------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[WOS_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kNoAllocMaxDevices = 64;
+constexpr size_t kNoAllocHostBytes =
+    (size_t)WOS_NOALLOC_MAX_ENVS * (sizeof(EnvP<float>) + sizeof(BatchEnv));
+
+inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// Host side of the no-allocation call: the device addresses of `scratch`,
+// one upload event per device, and static host staging for the tables (the
+// next call waits for the previous upload before rewriting it).  The mutex
+// serialises callers on the host; calls that overlap on one device's streams
+// still share that device's array.
+struct NoAlloc {
+    std::mutex mu;
+    unsigned char* dev[kNoAllocMaxDevices] = {};
+    hipEvent_t ev[kNoAllocMaxDevices] = {};
+    hipEvent_t pending = nullptr;
+};
+NoAlloc g_na;
+alignas(256) unsigned char g_na_host[kNoAllocHostBytes];
+int g_na_order[WOS_NOALLOC_MAX_ENVS];
+
+// Set-up on the current device, once: resolve the array's device address
+// and create the upload event.
+int noalloc_setup(int dev)
+{
+    if (dev < 0 || dev >= kNoAllocMaxDevices)
+        return fail(WOS_EINVAL, "device %d: the no-allocation call supports devices 0..%d", dev, kNoAllocMaxDevices - 1);
+    if (g_na.dev[dev]) return WOS_OK;
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "scratch address");
+    e = hipEventCreateWithFlags(&g_na.ev[dev], hipEventDisableTiming);
+    if (e != hipSuccess) return hip_fail(e, "scratch upload event");
+    g_na.dev[dev] = (unsigned char*)ptr;
+    return WOS_OK;
+}
+
+// Batched launch.  fixed = false: tables and partial sums in stream-ordered
+// device allocations.  fixed = true: everything in the device's `scratch`
+// array, nothing allocated (wos_estimate_batch_noalloc).
 int run_batch(const wos_domain* const* envs, int n_envs, const float* queries, const int64_t* q_offsets,
               const double* sigma, const double* eps, const int64_t* n_walks, uint64_t seed, float* out_u,
               float* out_grad, double* out_stats, const float* grad_u, float* out_dx, double* out_dsigma,
-              double* out_dg, const wos_options* opt, hipStream_t st, int force_upw, int force_gm,
-              int force_wpl)
+              double* out_dg, const wos_options* opt, hipStream_t st, const Tune* force, bool fixed)
 {
     wos_options o;
     int rc = read_opts(opt, o);
@@ -739,6 +797,9 @@ int run_batch(const wos_domain* const* envs, int n_envs, const float* queries, c
     if (n_envs < 0 || (n_envs > 0 && (!envs || !q_offsets || !sigma || !eps || !n_walks)))
         return fail(WOS_EINVAL, "envs, q_offsets, sigma, eps and n_walks are required");
     if (n_envs == 0) return WOS_OK;
+    if (fixed && n_envs > WOS_NOALLOC_MAX_ENVS)
+        return fail(WOS_EINVAL, "%d environments: the no-allocation call takes at most %d", n_envs,
+                    WOS_NOALLOC_MAX_ENVS);
     for (int e = 0; e < n_envs; ++e)
         if (n_walks[e] < 1 || n_walks[e] > (int64_t)1 << 31) return fail(WOS_EINVAL, "n_walks[%d] must be in [1, 2^31]", e);
     if (q_offsets[0] != 0) return fail(WOS_EINVAL, "q_offsets[0] must be 0");
@@ -752,7 +813,34 @@ int run_batch(const wos_domain* const* envs, int n_envs, const float* queries, c
     const bool bwd = grad_u != nullptr;
     if (bwd && (!out_dx || !out_dsigma || !out_dg))
         return fail(WOS_EINVAL, "out_dx, out_dsigma and out_dg are required with grad_u");
-    std::vector<EnvP<float>> hp(n_envs);
+
+    // host tables, contiguous: [EnvP x n_envs][BatchEnv x n_envs]
+    const size_t env_bytes = (size_t)n_envs * sizeof(EnvP<float>);
+    const size_t tab_bytes = env_bytes + (size_t)n_envs * sizeof(BatchEnv);
+    std::unique_lock<std::mutex> na_lock;
+    std::vector<unsigned char> host_vec;
+    std::vector<int> order_vec;
+    unsigned char* host_tab;
+    int* order;
+    int dev = 0;
+    if (fixed) {
+        na_lock = std::unique_lock<std::mutex>(g_na.mu);
+        WOS_HIP(hipGetDevice(&dev), "hipGetDevice");
+        if ((rc = noalloc_setup(dev))) return rc;
+        if (g_na.pending) {  // the previous call's upload still reads the staging
+            WOS_HIP(hipEventSynchronize(g_na.pending), "staging wait");
+            g_na.pending = nullptr;
+        }
+        host_tab = g_na_host;
+        order = g_na_order;
+    } else {
+        host_vec.resize(tab_bytes);
+        order_vec.resize(n_envs);
+        host_tab = host_vec.data();
+        order = order_vec.data();
+    }
+    EnvP<float>* hp = reinterpret_cast<EnvP<float>*>(host_tab);
+    BatchEnv* hb = reinterpret_cast<BatchEnv*>(host_tab + env_bytes);
     bool src = false;
     for (int e = 0; e < n_envs; ++e) {
         if ((rc = make_env<float>(envs[e], sigma[e], eps[e], seed, (uint32_t)e, o, hp[e]))) return rc;
@@ -762,26 +850,37 @@ int run_batch(const wos_domain* const* envs, int n_envs, const float* queries, c
     }
 
     BatchLayout L;
-    plan_batch(envs, q_offsets, n_envs, n_walks, kBatchStride, force_upw, force_gm, force_wpl,
-               (o.flags & WOS_FULL_SCAN) != 0, src,
+    plan_batch(envs, q_offsets, n_envs, n_walks, kBatchStride, force, (o.flags & WOS_FULL_SCAN) != 0, src, order, hb,
                L);
+    const size_t part_bytes = (size_t)std::max<int64_t>(L.total_units, 1) * nacc(kMaxDim) * sizeof(double);
 
     Scratch S(st);
-    // one upload: [EnvP x n_envs][BatchEnv x n_envs]
-    const size_t env_bytes = hp.size() * sizeof(EnvP<float>);
-    const size_t tab_bytes = env_bytes + L.benv.size() * sizeof(BatchEnv);
-    std::vector<unsigned char> host_tab(tab_bytes);
-    std::memcpy(host_tab.data(), hp.data(), env_bytes);
-    std::memcpy(host_tab.data() + env_bytes, L.benv.data(), L.benv.size() * sizeof(BatchEnv));
     unsigned char* d_tab;
     double* partials;
     unsigned* counter;
-    if ((rc = S.get(&d_tab, tab_bytes)) || (rc = S.get(&partials, (size_t)L.total_units * nacc(kMaxDim))) ||
-        (rc = S.get(&counter, 1)))
-        return rc;
-    if ((rc = upload(d_tab, host_tab.data(), tab_bytes, st))) return rc;
+    if (fixed) {
+        const size_t off_tab = 256, off_part = align256(off_tab + tab_bytes);
+        const size_t need = off_part + part_bytes;
+        if (need > (size_t)WOS_NOALLOC_SCRATCH_BYTES)
+            return fail(WOS_EINVAL,
+                        "the batch needs %zu bytes of scratch (%lld work units); the no-allocation call holds %zu",
+                        need, (long long)L.total_units, (size_t)WOS_NOALLOC_SCRATCH_BYTES);
+        unsigned char* base = g_na.dev[dev];
+        counter = reinterpret_cast<unsigned*>(base);
+        d_tab = base + off_tab;
+        partials = reinterpret_cast<double*>(base + off_part);
+        WOS_HIP(hipMemcpyAsync(d_tab, host_tab, tab_bytes, hipMemcpyHostToDevice, st), "table upload");
+        WOS_HIP(hipEventRecord(g_na.ev[dev], st), "hipEventRecord");
+        g_na.pending = g_na.ev[dev];
+    } else {
+        if ((rc = S.get(&d_tab, tab_bytes)) || (rc = S.get(&partials, part_bytes / sizeof(double))) ||
+            (rc = S.get(&counter, 1)))
+            return rc;
+        if ((rc = upload(d_tab, host_tab, tab_bytes, st))) return rc;
+    }
     const EnvP<float>* d_env = (const EnvP<float>*)d_tab;
     const BatchEnv* d_benv = (const BatchEnv*)(d_tab + env_bytes);
+    // the counter starts at 0 (a fill kernel: no memset node if the caller captures)
     WOS_HIP(launch_fill_u32(counter, 1, 0u, st), "fill");
     WOS_HIP(launch_persistent(bwd, src, L.grid, 256, d_env, d_benv, n_envs, queries, L.total_units,
                               (uint32_t)seed, (uint32_t)(seed >> 32), nullptr, counter, partials, st),
@@ -1186,7 +1285,17 @@ int wos_estimate_batch(const wos_domain* const* envs, int n_envs, const float* q
                        double* out_dg, const wos_options* opt, void* stream)
 {
     return run_batch(envs, n_envs, queries, q_offsets, sigma, eps, n_walks, seed, out_u, out_grad, out_stats,
-                     grad_u, out_dx, out_dsigma, out_dg, opt, (hipStream_t)stream, 0, 0, 0);
+                     grad_u, out_dx, out_dsigma, out_dg, opt, (hipStream_t)stream, nullptr, false);
+}
+
+int wos_estimate_batch_noalloc(const wos_domain* const* envs, int n_envs, const float* queries,
+                               const int64_t* q_offsets, const double* sigma, const double* eps,
+                               const int64_t* n_walks, uint64_t seed, float* out_u, float* out_grad,
+                               double* out_stats, const float* grad_u, float* out_dx, double* out_dsigma,
+                               double* out_dg, const wos_options* opt, void* stream)
+{
+    return run_batch(envs, n_envs, queries, q_offsets, sigma, eps, n_walks, seed, out_u, out_grad, out_stats,
+                     grad_u, out_dx, out_dsigma, out_dg, opt, (hipStream_t)stream, nullptr, true);
 }
 
 int wos_debug_walks(const wos_domain* D, const double* query, uint32_t q_index, int64_t w0, int64_t n, double sigma,
@@ -1327,7 +1436,9 @@ int wos_plan_create(const wos_domain* D, float* x, int64_t n_starts, int64_t n_w
     const int64_t qoff[2] = {0, n_starts};
     const int64_t nw[1] = {n_walks};
     BatchLayout L;
-    plan_batch(envs, qoff, 1, nw, D->d, 0, 0, 0, (o.flags & WOS_FULL_SCAN) != 0, D->has_src, L);
+    BatchEnv benv1;
+    int order1;
+    plan_batch(envs, qoff, 1, nw, D->d, nullptr, (o.flags & WOS_FULL_SCAN) != 0, D->has_src, &order1, &benv1, L);
     const int64_t S = n_starts;
     if (e == hipSuccess) e = hipMalloc(&P->u, S * sizeof(float));
     if (e == hipSuccess) e = hipMalloc(&P->grad, S * kBatchStride * sizeof(float));
@@ -1345,7 +1456,7 @@ int wos_plan_create(const wos_domain* D, float* x, int64_t n_starts, int64_t n_w
     if (e == hipSuccess) e = hipMalloc(&P->env, sizeof(EnvP<float>));
     if (e == hipSuccess) e = hipMalloc(&P->benv, sizeof(BatchEnv));
     if (e == hipSuccess) e = hipMemcpy(P->env, &P->henv, sizeof(EnvP<float>), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(P->benv, L.benv.data(), sizeof(BatchEnv), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(P->benv, &benv1, sizeof(BatchEnv), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = launch_fill_f64(P->path_len, S, 0.0, st);
     if (e == hipSuccess) e = launch_fill_u32((unsigned*)P->stalls, S, 0u, st);
     if (e == hipSuccess) e = launch_fill_u32((unsigned*)P->status, S, 0u, st);
@@ -1488,8 +1599,9 @@ int wos_autotune(int d, int64_t M, int64_t Q, int64_t n_walks, const char* cache
             // warm-up then one timed launch
             for (int rep = 0; rep < 2 && !rc && e == hipSuccess; ++rep) {
                 if (rep == 1) e = hipEventRecord(e0, nullptr);
+                const Tune force{upw, gm, wpl};
                 rc = run_batch(envs, 1, dq, qoff, &sig, &ep, nw, 1234 + rep, du, dgr, nullptr, dub, ddx, dds, ddg,
-                               nullptr, nullptr, upw, gm, wpl);
+                               nullptr, nullptr, &force, false);
                 if (rep == 1 && e == hipSuccess) e = hipEventRecord(e1, nullptr);
             }
             if (e == hipSuccess && !rc) e = hipEventSynchronize(e1);

@@ -205,7 +205,8 @@ def test_binding_constants_match_the_header(B):
     defs = dict(re.findall(r"^#define\s+(WOS_[A-Z0-9_]+)\s+\(?(-?\d+)u?\)?", src, flags=re.M))
     shared = [k for k in defs if hasattr(B, k)]
     assert {"WOS_FP64", "WOS_FULL_SCAN", "WOS_SCALAR_CULL", "WOS_WAVE_SCAN", "WOS_OUT_FP64",
-            "WOS_EINVAL", "WOS_ENOTSUP", "WOS_OUTER_BOX"} <= set(shared)
+            "WOS_EINVAL", "WOS_ENOTSUP", "WOS_OUTER_BOX", "WOS_NOALLOC_SCRATCH_BYTES",
+            "WOS_NOALLOC_MAX_ENVS"} <= set(shared)
     for k in shared:
         assert int(defs[k]) == getattr(B, k), k
 
@@ -218,3 +219,21 @@ def test_option_flags_are_checked_before_device_work(B):
     assert b"unknown flags" in B.lib.wos_last_error()
     opt = B.options(out_fp64=True)
     assert B.lib.wos_varadhan(None, None, 0, 2, 2, 1.0, None, None, C.byref(opt), None) == B.WOS_ENOTSUP
+
+
+def test_noalloc_batch_rejects_too_many_envs_on_the_host(B):
+    """The no-allocation batch call takes at most WOS_NOALLOC_MAX_ENVS
+    environments and says so before any device work (the handles are not
+    even read)."""
+    n = B.WOS_NOALLOC_MAX_ENVS + 1
+    hs = (C.c_void_p * n)()
+    qo = np.zeros(n + 1, dtype=np.int64)
+    f = np.ones(n)
+    nw = np.ones(n, dtype=np.int64)
+    rc = B.lib.wos_estimate_batch_noalloc(hs, n, None, qo.ctypes.data_as(C.POINTER(C.c_int64)),
+                                          f.ctypes.data_as(C.POINTER(C.c_double)),
+                                          f.ctypes.data_as(C.POINTER(C.c_double)),
+                                          nw.ctypes.data_as(C.POINTER(C.c_int64)), 0, None, None, None, None,
+                                          None, None, None, None, None)
+    assert rc == B.WOS_EINVAL
+    assert b"at most 1024" in B.lib.wos_last_error()

@@ -1,0 +1,97 @@
+"""wos_estimate_batch_noalloc, called through the C ABI, against
+wos_estimate_batch: the same persistent launch with its tables, work-unit
+counter and partial sums in the library's fixed per-device array instead of
+fresh device allocations, so the outputs must be bitwise those of the
+allocating call.  Two calls in a row, the second with a smaller batch (the
+array keeps the first call's contents), forward + backward and forward only;
+a batch beyond the array's size is rejected before anything runs."""
+import numpy as np
+import pytest
+
+from paper_2406_01713_amd import scenes as S
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2406_01713_amd import binding
+    return binding
+
+
+def _batch(B, envs, noalloc, bwd, seed=11):
+    import torch
+    doms = [B.Domain(e) for e in envs]
+    off = np.concatenate([[0], np.cumsum([len(e["queries"]) for e in envs])]).astype(np.int64)
+    n = int(off[-1])
+    qp = np.zeros((n, 8), dtype=np.float32)
+    for e, s in enumerate(envs):
+        qp[off[e]:off[e + 1], :s["d"]] = s["queries"]
+    q = torch.as_tensor(qp, device="cuda")
+    # outputs start as NaN so that a row the call does not write shows up
+    u = torch.full((n,), float("nan"), device="cuda")
+    g = torch.full((n, 8), float("nan"), device="cuda")
+    st = torch.full((n, 15), float("nan"), dtype=torch.float64, device="cuda")
+    kw = {}
+    if bwd:
+        ub = torch.as_tensor(np.random.default_rng(3).normal(size=n).astype(np.float32), device="cuda")
+        kw = dict(grad_u=ub, out_dx=torch.full((n, 8), float("nan"), device="cuda"),
+                  out_dsigma=torch.full((len(envs),), float("nan"), dtype=torch.float64, device="cuda"),
+                  out_dg=torch.full((len(envs),), float("nan"), dtype=torch.float64, device="cuda"))
+    B.wos_estimate_batch(doms, q, off, [e["sigma"] for e in envs], [e["eps"] for e in envs],
+                         [e["n_walks"] for e in envs], seed, u, g, st, noalloc=noalloc, **kw)
+    torch.cuda.synchronize()
+    out = {"u": u.cpu().numpy(), "g": g.cpu().numpy(), "st": st.cpu().numpy()}
+    for k in ("out_dx", "out_dsigma", "out_dg"):
+        if k in kw:
+            out[k] = kw[k].cpu().numpy()
+    return out
+
+
+def _envs(n_envs, q_cap, n_walks):
+    envs = [S.scene_c4_env(e, n_walks=n_walks, seed=5, q_cap=q_cap) for e in range(n_envs)]
+    envs.append(S.scene_spheres(8, n_queries=q_cap, n_walks=n_walks, seed=5))
+    return [S.with_bdata(e, 2, ak=S.plane_wave_k(e["d"], e["sigma"], seed=i)) for i, e in enumerate(envs)]
+
+
+def _same(a, b, what):
+    for k in a:
+        assert np.array_equal(a[k], b[k], equal_nan=False), (what, k)
+        assert np.all(np.isfinite(a[k])), (what, k)
+
+
+def test_noalloc_matches_the_allocating_call_twice(B):
+    big = _envs(12, 48, 512)     # d 2..8, uneven obstacle and query counts
+    small = _envs(3, 6, 256)
+    a = _batch(B, big, True, True)
+    b = _batch(B, big, False, True)
+    _same(a, b, "first call, fwd + bwd")
+    assert np.all(a["u"] > 0)   # plane-wave data: every query has signal
+    a = _batch(B, small, True, True)
+    b = _batch(B, small, False, True)
+    _same(a, b, "second, smaller call, fwd + bwd")
+    a = _batch(B, small, True, False)
+    b = _batch(B, small, False, False)
+    _same(a, b, "forward only")
+
+
+def test_noalloc_rejects_a_batch_beyond_its_array(B):
+    """400000 queries of 64 walks are 400000 work units of 200 bytes: more
+    than the 64 MiB array; the call returns WOS_EINVAL and writes nothing."""
+    import torch
+    s = S.scene_spheres(3, n_queries=1, n_walks=64, seed=1)
+    n = 400000
+    q = torch.zeros(n, 8, device="cuda")
+    q[:, :3] = torch.as_tensor(s["queries"][0], dtype=torch.float32, device="cuda")
+    u = torch.full((n,), -1.0, device="cuda")
+    with pytest.raises(B.WosError) as err:
+        B.wos_estimate_batch([B.Domain(s)], q, np.array([0, n], dtype=np.int64), [s["sigma"]], [s["eps"]],
+                             [64], 1, u, noalloc=True)
+    assert err.value.code == B.WOS_EINVAL and "bytes of scratch" in str(err.value)
+    torch.cuda.synchronize()
+    assert bool(torch.all(u == -1.0))
+    # the array still serves a batch that fits
+    small = _envs(2, 4, 128)
+    _same(_batch(B, small, True, True), _batch(B, small, False, True), "after the rejected call")
