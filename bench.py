@@ -291,7 +291,7 @@ def launch_work(envs, off, stats):
     return ws, valu, mfma
 
 
-def ragged_c4(B, torch, st, reps=3, plain_reps=2):
+def ragged_c4(B, torch, st, reps=3, plain_reps=2, tune_cache=None):
     """The full ragged batch (512 envs, d uniform in 2..7, 16-2048 spheres,
     1-4096 queries, sigma U[0.5, 8], 2048 walks): one persistent launch,
     forward only and fused forward + backward (u-bar = 1), against the plain
@@ -301,6 +301,10 @@ def ragged_c4(B, torch, st, reps=3, plain_reps=2):
     envs = S.scene_c4()
     draw_s = time.perf_counter() - t
     bat = Batch(B, envs, torch)
+    t = time.perf_counter()
+    tune = B.wos_autotune_batch(bat.doms, bat.q, bat.off, bat.sig, bat.eps, bat.nw, bat.seed, fused=True,
+                                cache_path=tune_cache)
+    tune["search_s"] = time.perf_counter() - t
     fwd_ms, fwd_min = timed(lambda: bat.run(bwd=False), reps, torch, st)
     ws_f, valu_f, mfma_f = launch_work(envs, bat.off, bat.st.cpu().numpy())
     fused_ms, fused_min = timed(lambda: bat.run(), reps, torch, st)
@@ -332,7 +336,8 @@ def ragged_c4(B, torch, st, reps=3, plain_reps=2):
                      "repeats": plain_reps, "max_rel_diff_u_vs_batched": diff},
            "batched_vs_plain_forward": pf_ms / fwd_ms,
            "batched_vs_plain_fwd_plus_bwd": (pf_ms + pb_ms) / fused_ms,
-           "batched_vs_plain_like_for_like": pb_ms / fused_ms}
+           "batched_vs_plain_like_for_like": pb_ms / fused_ms,
+           "autotune": dict(tune, gain_vs_default=tune["ms_default"] / fused_ms)}
     del pl, bat
     return res
 
@@ -559,6 +564,9 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--plain-reps", type=int, default=3, help="timed repeats of the plain per-env path")
     ap.add_argument("--no-c4", action="store_true", help="skip the full ragged batch and the 6-D forward set")
+    ap.add_argument("--no-tune", action="store_true", help="time the built-in launch shape (no autotune search)")
+    ap.add_argument("--tune-cache", default=None, help="also write the searched launch shapes to this JSON file")
+    ap.add_argument("--load-tune", default=None, help="use the launch shapes of this JSON file (no search)")
     ap.add_argument("--full-scan", action="store_true",
                     help="scan every obstacle each step (no cluster culling): same results, more work")
     ap.add_argument("--no-cpu", action="store_true")
@@ -607,6 +615,19 @@ def main():
         torch.cuda.synchronize()
         log(f"calibration copy: {args.calib_copy_mib} MiB x 3")
 
+    tune = None
+    if args.load_tune:
+        # a shape chosen by an earlier search (e.g. for a profiled run)
+        B.wos_set_autotune_cache(args.load_tune)
+        log(f"launch shapes loaded from {args.load_tune}")
+    elif not args.no_tune:
+        # launch shape searched on this batch (fused fwd + bwd); the timed
+        # launches below use it (the library keeps it for this batch mix)
+        t = time.perf_counter()
+        tune = B.wos_autotune_batch(bat.doms, bat.q, bat.off, bat.sig, bat.eps, bat.nw, bat.seed, fused=True,
+                                    cache_path=args.tune_cache)
+        tune["search_s"] = time.perf_counter() - t
+        log(f"autotune: {tune}")
     for _ in range(args.warmup):
         bat.run()
     torch.cuda.synchronize()
@@ -689,6 +710,11 @@ def main():
                                       "of this code's instruction types in 'measured'",
                         "measured": ceilings,
                         "kernel_hash": khash}}
+    if tune is not None:
+        out["autotune"] = dict(tune, basis="wos_autotune_batch on this batch before timing: coordinate descent "
+                                            "over waves per block, units per wave, grid multiple, walks per lane; "
+                                            "ms_default = one launch with the built-in shape (4, 4, 1, 2)",
+                               gain_vs_default=tune["ms_default"] / ms_step)
 
     if not args.no_plain:
         t = time.perf_counter()
@@ -710,7 +736,7 @@ def main():
 
     if not args.no_c4:
         t = time.perf_counter()
-        out["ragged_c4"] = ragged_c4(B, torch, st)
+        out["ragged_c4"] = ragged_c4(B, torch, st, tune_cache=args.tune_cache)
         r = out["ragged_c4"]
         log(f"ragged C4: fused {r['fused_fwd_bwd']['ms']:.1f} ms ({r['fused_fwd_bwd']['walk_steps_per_s']:.3e} "
             f"walk-steps/s), forward {r['forward']['ms']:.1f} ms; plain fwd {r['plain']['forward_ms']:.1f} ms, "

@@ -357,11 +357,45 @@ int wos_plan_read(wos_plan* plan, float* u, float* grad, double* path_len, int32
 void wos_plan_destroy(wos_plan* plan);
 
 /*
- * wos_autotune -- time the persistent kernel's launch shapes (work units per
- * resident wave 1-16, grid of 1 or 2 times the resident blocks, at least 1, 2
- * or 4 walks per lane in a unit) on a synthetic scene of dimension d with M
- * sphere obstacles and Q queries, and record the fastest in the cache file
- * (JSON, created or updated) under the bucket of (d, M, Q).  Subsequent batched launches in this process read the cache at
+ * Launch shape of the persistent batched kernel, as searched by the
+ * autotuner (no passage of the paper: the launch layout is this library's).
+ */
+typedef struct {
+    int waves_per_block;  /* 1, 2 or 4: blocks of 64, 128 or 256 threads */
+    int units_per_wave;   /* work units (query, walk range) per resident wave */
+    int grid_mult;        /* grid = grid_mult x the resident blocks of the device */
+    int walks_per_lane;   /* least walks each lane takes from a work unit */
+    double ms_default;    /* launch time with the built-in shape (4, 4, 1, 2) */
+    double ms_best;       /* launch time with the chosen shape */
+    int tried;            /* shapes timed */
+} wos_tune_result;
+
+/*
+ * wos_autotune_batch -- time the persistent launch of the caller's own batch
+ * (arguments as wos_estimate_batch; fused != 0: forward + backward with
+ * u-bar = 1, else forward only) for launch shapes reached by coordinate
+ * descent from the built-in one: waves per block {1, 2, 4}, units per wave
+ * {1, 2, 4, 8, 16}, grid multiple {1, 2}, walks per lane {1, 2, 4}, one
+ * parameter at a time with the others held; a shape must beat the best by
+ * more than 0.5 % to replace it.  The best shape is recorded for this batch
+ * mix (the multiset of its environments' dimension and log2 buckets of
+ * obstacle, query and walk counts), in memory for the batched calls of this
+ * process and, when cache_path is not NULL, in that JSON file (created or
+ * updated).  out (nullable) receives the shape and the two launch times.
+ * Blocks the calling thread; allocates its own output buffers.
+ * Errors: as wos_estimate_batch; WOS_EINVAL without queries.
+ */
+int wos_autotune_batch(const wos_domain* const* envs, int n_envs, const float* queries,
+                       const int64_t* q_offsets, const double* sigma, const double* eps,
+                       const int64_t* n_walks, uint64_t seed, int fused, const char* cache_path,
+                       wos_tune_result* out);
+
+/*
+ * wos_autotune -- the same search on a synthetic scene of dimension d with
+ * M sphere obstacles and Q queries (fused forward + backward), recorded in
+ * the cache file (JSON, created or updated) under the bucket of (d, M, Q).
+ * Batched launches look up their batch mix first, then the bucket of their
+ * heaviest environment, else use the built-in shape; the cache is read from
  * cache_path (or $WOS_AUTOTUNE_CACHE when wos_set_autotune_cache was not
  * called).  Blocks the calling thread (synchronises the device).
  */

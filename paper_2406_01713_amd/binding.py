@@ -30,7 +30,8 @@ MAX_DIM = 8
 
 EXPORTED = ["wos_create_domain", "wos_destroy_domain", "wos_domain_dim", "wos_estimate",
             "wos_backward", "wos_estimate_batch", "wos_estimate_batch_noalloc", "wos_plan_create", "wos_plan_step",
-            "wos_plan_buffers", "wos_plan_read", "wos_plan_destroy", "wos_autotune", "wos_set_autotune_cache",
+            "wos_plan_buffers", "wos_plan_read", "wos_plan_destroy", "wos_autotune", "wos_autotune_batch",
+            "wos_set_autotune_cache",
             "wos_debug_walks", "wos_debug_clusters", "wos_varadhan", "wos_microbench", "wos_last_error"]
 
 
@@ -76,6 +77,12 @@ class Options(C.Structure):
                 ("reserved", C.c_uint32)]
 
 
+class TuneResult(C.Structure):
+    _fields_ = [("waves_per_block", C.c_int), ("units_per_wave", C.c_int), ("grid_mult", C.c_int),
+                ("walks_per_lane", C.c_int), ("ms_default", C.c_double), ("ms_best", C.c_double),
+                ("tried", C.c_int)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2406_01713_amd.build` "
@@ -104,6 +111,8 @@ def _load():
     L.wos_plan_destroy.argtypes = [vp]
     L.wos_plan_destroy.restype = None
     L.wos_autotune.argtypes = [C.c_int, i64, i64, i64, C.c_char_p]
+    L.wos_autotune_batch.argtypes = [C.POINTER(vp), C.c_int, vp, C.POINTER(i64), dp, dp, C.POINTER(i64), u64,
+                                     C.c_int, C.c_char_p, C.POINTER(TuneResult)]
     L.wos_set_autotune_cache.argtypes = [C.c_char_p]
     L.wos_debug_walks.argtypes = [vp, dp, u32, i64, i64, C.c_double, C.c_double, u64,
                                   C.POINTER(Options), dp]
@@ -322,6 +331,23 @@ def wos_microbench(which):
 def wos_autotune(d, n_obstacles, n_queries, n_walks, cache_path):
     check(lib.wos_autotune(int(d), int(n_obstacles), int(n_queries), int(n_walks),
                            str(cache_path).encode()))
+
+
+def wos_autotune_batch(doms, queries, q_offsets, sigma, eps, n_walks, seed, fused=True, cache_path=None):
+    """Search the persistent launch's shape on this batch (wos_autotune_batch);
+    returns the chosen shape and the launch times (ms) of the built-in and
+    the chosen shape."""
+    n = len(doms)
+    hs = (C.c_void_p * n)(*[dm.handle.value for dm in doms])
+    qo = np.ascontiguousarray(np.asarray(q_offsets, dtype=np.int64))
+    sg = _f64(sigma)
+    ep = _f64(eps)
+    nw = np.ascontiguousarray(np.broadcast_to(np.asarray(n_walks, dtype=np.int64), (n,)))
+    r = TuneResult()
+    check(lib.wos_autotune_batch(hs, n, _ptr(queries), qo.ctypes.data_as(C.POINTER(C.c_int64)), _dp(sg), _dp(ep),
+                                 nw.ctypes.data_as(C.POINTER(C.c_int64)), int(seed), int(bool(fused)),
+                                 None if cache_path is None else str(cache_path).encode(), C.byref(r)))
+    return {k: getattr(r, k) for k, _ in TuneResult._fields_}
 
 
 def wos_set_autotune_cache(cache_path):

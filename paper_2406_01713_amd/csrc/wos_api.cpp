@@ -560,16 +560,19 @@ int upload(void* dst, const void* src, size_t bytes, hipStream_t st)
 }
 
 // ------------------------------------------------------------------------
-// Autotune cache: per (d, obstacle bucket, query bucket) the fastest number
-// of work units per resident wave and persistent-grid multiplier.
+// Autotune cache: launch shapes of the persistent kernel keyed by the batch
+// mix (the multiset of its environments' dimension and log2 buckets of
+// obstacle, query and walk counts) or, from the synthetic single-scene
+// tuner, by the (d, obstacle bucket, query bucket) of the heaviest env.
 // ------------------------------------------------------------------------
 struct Tune {
     int units_per_wave = 4;
     int grid_mult = 1;
-    int walks_per_lane = 2;  // least walks per lane in a work unit (lane refill needs 2)
+    int walks_per_lane = 2;   // least walks per lane in a work unit (lane refill needs 2)
+    int waves_per_block = 4;  // block of 64, 128 or 256 threads
 };
 std::mutex g_tune_mu;
-std::map<std::string, Tune> g_tune;
+std::map<std::string, Tune, std::less<>> g_tune;  // transparent: lookups by char* allocate nothing
 bool g_tune_loaded = false;
 std::string g_tune_path;
 
@@ -583,11 +586,24 @@ int log2_bucket(int64_t v)
     return b;
 }
 
-std::string tune_key(int d, int64_t M, int64_t Q)
+void tune_key(char (&k)[48], int d, int64_t M, int64_t Q)
 {
-    char k[64];
     snprintf(k, sizeof(k), "d%d_m%d_q%d", d, log2_bucket(std::max<int64_t>(M, 1)), log2_bucket(std::max<int64_t>(Q, 1)));
-    return k;
+}
+
+uint64_t mix64(uint64_t z)
+{
+    z += 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+bool valid_tune(const Tune& t)
+{
+    return t.units_per_wave > 0 && t.units_per_wave <= 64 && t.grid_mult > 0 && t.grid_mult <= 8 &&
+           t.walks_per_lane > 0 && t.walks_per_lane <= 64 &&
+           (t.waves_per_block == 1 || t.waves_per_block == 2 || t.waves_per_block == 4);
 }
 
 void load_tune_locked(const char* path)
@@ -598,24 +614,34 @@ void load_tune_locked(const char* path)
     if (!path || !*path) return;
     FILE* f = fopen(path, "r");
     if (!f) return;
-    char line[256];
+    char line[320];
     while (fgets(line, sizeof(line), f)) {
         char key[64];
-        int upw = 0, gm = 0, wpl = 2;
-        // one entry per line: "key": {"units_per_wave": U, "grid_mult": G, "walks_per_lane": W},
-        // (W absent in older files: 2)
-        const int n = sscanf(line, " \"%63[^\"]\": {\"units_per_wave\": %d, \"grid_mult\": %d, \"walks_per_lane\": %d}",
-                             key, &upw, &gm, &wpl);
-        if (n >= 3 && upw > 0 && gm > 0 && wpl > 0 && wpl <= 64) g_tune[key] = Tune{upw, gm, n == 4 ? wpl : 2};
+        Tune t;
+        // one entry per line: "key": {"units_per_wave": U, "grid_mult": G,
+        // "walks_per_lane": W, "waves_per_block": B}, (W, B absent in older
+        // files: 2, 4)
+        const int n = sscanf(line,
+                             " \"%63[^\"]\": {\"units_per_wave\": %d, \"grid_mult\": %d, \"walks_per_lane\": %d, "
+                             "\"waves_per_block\": %d}",
+                             key, &t.units_per_wave, &t.grid_mult, &t.walks_per_lane, &t.waves_per_block);
+        if (n < 4) t.walks_per_lane = 2;
+        if (n < 5) t.waves_per_block = 4;
+        if (n >= 3 && valid_tune(t)) g_tune[key] = t;
     }
     fclose(f);
 }
 
-Tune lookup_tune(int d, int64_t M, int64_t Q)
+// The batch mix's entry, else the heaviest env's bucket, else the defaults.
+Tune lookup_tune(const char* mix, int d, int64_t M, int64_t Q)
 {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     if (!g_tune_loaded) load_tune_locked(getenv("WOS_AUTOTUNE_CACHE"));
-    auto it = g_tune.find(tune_key(d, M, Q));
+    auto it = g_tune.find(mix);
+    if (it != g_tune.end()) return it->second;
+    char k[48];
+    tune_key(k, d, M, Q);
+    it = g_tune.find(k);
     if (it != g_tune.end()) return it->second;
     return Tune{};
 }
@@ -627,9 +653,10 @@ int save_tune_locked(const char* path)
     fprintf(f, "{\n");
     size_t i = 0;
     for (auto& kv : g_tune) {
-        fprintf(f, "  \"%s\": {\"units_per_wave\": %d, \"grid_mult\": %d, \"walks_per_lane\": %d}%s\n",
+        fprintf(f, "  \"%s\": {\"units_per_wave\": %d, \"grid_mult\": %d, \"walks_per_lane\": %d, "
+                   "\"waves_per_block\": %d}%s\n",
                 kv.first.c_str(), kv.second.units_per_wave, kv.second.grid_mult, kv.second.walks_per_lane,
-                (++i < g_tune.size()) ? "," : "");
+                kv.second.waves_per_block, (++i < g_tune.size()) ? "," : "");
     }
     fprintf(f, "}\n");
     fclose(f);
@@ -647,9 +674,26 @@ double unit_cost(const wos_domain* D, int64_t wps)
     return per_step * steps[d] * (double)wps;
 }
 
+// Key of a batch mix: the sum over envs of a hash of (d, log2 buckets of
+// obstacles, queries and walks, point source), so the order of the envs does
+// not matter and nothing is allocated.
+void mix_key(char (&k)[48], const wos_domain* const* envs, const int64_t* q_off, int n_envs, const int64_t* n_walks)
+{
+    uint64_t h = 0;
+    for (int e = 0; e < n_envs; ++e) {
+        const wos_domain* D = envs[e];
+        const uint64_t v = (uint64_t)D->d | ((uint64_t)log2_bucket(std::max<int64_t>(D->n_sph + D->n_box + D->n_arm, 1)) << 8) |
+                           ((uint64_t)log2_bucket(std::max<int64_t>(q_off[e + 1] - q_off[e], 1)) << 16) |
+                           ((uint64_t)log2_bucket(n_walks[e]) << 24) | ((uint64_t)(D->has_src ? 1 : 0) << 32);
+        h += mix64(v);
+    }
+    snprintf(k, sizeof(k), "mix_%d_%016llx", n_envs, (unsigned long long)h);
+}
+
 struct BatchLayout {
     int64_t total_units = 0;
     int grid = 0;
+    int block = 256;
 };
 
 // Work units: each query's walks are split into `splits` ranges so that the
@@ -662,7 +706,6 @@ void plan_batch(const wos_domain* const* envs, const int64_t* q_off, int n_envs,
                 int q_stride, const Tune* force, bool full_scan, bool src, int* order, BatchEnv* benv,
                 BatchLayout& L)
 {
-    const int block = 256;
     int64_t sumQW = 0, maxM = 0, heavyQ = 0, maxW = 1;
     int heavy_d = 2;
     double heavy = -1;
@@ -678,11 +721,16 @@ void plan_batch(const wos_domain* const* envs, const int64_t* q_off, int n_envs,
             heavyQ = q;
         }
     }
-    Tune t = lookup_tune(heavy_d, maxM, heavyQ);
+    char mk[48];
+    mix_key(mk, envs, q_off, n_envs, n_walks);
+    Tune t = lookup_tune(mk, heavy_d, maxM, heavyQ);
     if (force && force->units_per_wave > 0) t.units_per_wave = force->units_per_wave;
     if (force && force->grid_mult > 0) t.grid_mult = force->grid_mult;
     if (force && force->walks_per_lane > 0) t.walks_per_lane = force->walks_per_lane;
+    if (force && force->waves_per_block > 0) t.waves_per_block = force->waves_per_block;
+    const int block = t.waves_per_block * kWave;
     const int resident_blocks = persistent_resident_blocks(true, src, block);
+    L.block = block;
     L.grid = std::max(1, resident_blocks * t.grid_mult);
     const int64_t waves = (int64_t)L.grid * (block / kWave);
     const int64_t target = waves * t.units_per_wave;
@@ -882,12 +930,111 @@ int run_batch(const wos_domain* const* envs, int n_envs, const float* queries, c
     const BatchEnv* d_benv = (const BatchEnv*)(d_tab + env_bytes);
     // the counter starts at 0 (a fill kernel: no memset node if the caller captures)
     WOS_HIP(launch_fill_u32(counter, 1, 0u, st), "fill");
-    WOS_HIP(launch_persistent(bwd, src, L.grid, 256, d_env, d_benv, n_envs, queries, L.total_units,
+    WOS_HIP(launch_persistent(bwd, src, L.grid, L.block, d_env, d_benv, n_envs, queries, L.total_units,
                               (uint32_t)seed, (uint32_t)(seed >> 32), nullptr, counter, partials, st),
             "persistent walk kernel");
     WOS_HIP(launch_finalize_batch(bwd, d_benv, n_envs, partials, grad_u, out_u, out_grad, kBatchStride,
                                   out_stats, out_dx, out_dsigma, out_dg, nullptr, counter, st),
             "batch finalize");
+    return WOS_OK;
+}
+
+// Launch-shape search on a batch: the persistent launch (forward + backward
+// with u-bar = 1 when fused) timed with HIP events for shapes reached by
+// coordinate descent from the built-in shape.  Each of waves per block,
+// units per wave, grid multiple and walks per lane in turn runs over its
+// candidate values with the others held; a shape replaces the best only when
+// it is faster by more than 0.5 % (launch times repeat to about 0.1 %), and a
+// second pass runs when the first moved.  One untimed launch comes first.
+// Output buffers are allocated here (this is a set-up call).
+struct TuneRun {
+    Tune best;
+    double ms_default = 0.0, ms_best = 0.0;
+    int tried = 0;
+};
+
+int tune_batch(const wos_domain* const* envs, int n_envs, const float* queries, const int64_t* q_off,
+               const double* sigma, const double* eps, const int64_t* n_walks, uint64_t seed, bool fused,
+               TuneRun& out)
+{
+    const int64_t sumQ = q_off[n_envs];
+    if (sumQ < 1) return fail(WOS_EINVAL, "the batch has no queries");
+    float *du = nullptr, *dg = nullptr, *dub = nullptr, *ddx = nullptr;
+    double *dds = nullptr, *ddg = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipStream_t st = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipMalloc(&du, sumQ * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc(&dg, sumQ * kBatchStride * sizeof(float));
+    if (e == hipSuccess && fused) e = hipMalloc(&dub, sumQ * sizeof(float));
+    if (e == hipSuccess && fused) e = hipMalloc(&ddx, sumQ * kBatchStride * sizeof(float));
+    if (e == hipSuccess && fused) e = hipMalloc(&dds, n_envs * sizeof(double));
+    if (e == hipSuccess && fused) e = hipMalloc(&ddg, n_envs * sizeof(double));
+    if (e == hipSuccess && fused) e = launch_fill_u32((unsigned*)dub, sumQ, 0x3f800000u, st);  // u-bar = 1.0f
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    int rc = WOS_OK;
+    auto time_one = [&](const Tune& t, double& ms) {
+        if (e != hipSuccess || rc) return;
+        e = hipEventRecord(e0, st);
+        if (e == hipSuccess)
+            rc = run_batch(envs, n_envs, queries, q_off, sigma, eps, n_walks, seed, du, dg, nullptr, dub, ddx, dds,
+                           ddg, nullptr, st, &t, false);
+        if (e == hipSuccess && !rc) e = hipEventRecord(e1, st);
+        if (e == hipSuccess && !rc) e = hipEventSynchronize(e1);
+        float f = 0.0f;
+        if (e == hipSuccess && !rc) e = hipEventElapsedTime(&f, e0, e1);
+        ms = f;
+    };
+    Tune cur;
+    double best_ms = 0.0, ms = 0.0;
+    time_one(cur, ms);  // untimed: first launch of the shape
+    time_one(cur, best_ms);
+    out.ms_default = best_ms;
+    out.tried = 1;
+    std::vector<std::pair<Tune, double>> seen{{cur, best_ms}};
+    auto same = [](const Tune& a, const Tune& b) {
+        return a.units_per_wave == b.units_per_wave && a.grid_mult == b.grid_mult &&
+               a.walks_per_lane == b.walks_per_lane && a.waves_per_block == b.waves_per_block;
+    };
+    static const int wpbs[] = {1, 2, 4}, upws[] = {1, 2, 4, 8, 16}, gms[] = {1, 2}, wpls[] = {1, 2, 4};
+    for (int pass = 0; pass < 2 && e == hipSuccess && !rc; ++pass) {
+        bool moved = false;
+        for (int prm = 0; prm < 4; ++prm) {
+            const int* vals = prm == 0 ? wpbs : prm == 1 ? upws : prm == 2 ? gms : wpls;
+            const int nv = prm == 0 ? 3 : prm == 1 ? 5 : prm == 2 ? 2 : 3;
+            for (int i = 0; i < nv && e == hipSuccess && !rc; ++i) {
+                Tune c = cur;
+                (prm == 0 ? c.waves_per_block : prm == 1 ? c.units_per_wave : prm == 2 ? c.grid_mult
+                                                                                        : c.walks_per_lane) = vals[i];
+                double m = -1.0;
+                for (auto& s : seen)
+                    if (same(s.first, c)) m = s.second;
+                if (m < 0.0) {
+                    time_one(c, m);
+                    seen.push_back({c, m});
+                    ++out.tried;
+                }
+                if (e == hipSuccess && !rc && m < best_ms * (1.0 - 0.005)) {
+                    cur = c;
+                    best_ms = m;
+                    moved = true;
+                }
+            }
+        }
+        if (!moved) break;
+    }
+    out.best = cur;
+    out.ms_best = best_ms;
+    if (st) (void)hipStreamSynchronize(st);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    void* bufs[] = {du, dg, dub, ddx, dds, ddg};
+    for (void* b : bufs)
+        if (b) (void)hipFree(b);
+    if (st) (void)hipStreamDestroy(st);
+    if (rc) return rc;
+    if (e != hipSuccess) return hip_fail(e, "autotune");
     return WOS_OK;
 }
 
@@ -1471,7 +1618,7 @@ int wos_plan_create(const wos_domain* D, float* x, int64_t n_starts, int64_t n_w
     // capture [fused forward + backward walks, finalize, update]
     e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        hipError_t e1 = launch_persistent(true, D->has_src, L.grid, 256, P->env, P->benv, 1, x, L.total_units,
+        hipError_t e1 = launch_persistent(true, D->has_src, L.grid, L.block, P->env, P->benv, 1, x, L.total_units,
                                           P->henv.key0, P->henv.key1, P->step, P->counter, P->partials, st);
         hipError_t e2 = launch_finalize_batch(true, P->benv, 1, P->partials, P->ubar, P->u, P->grad,
                                               kBatchStride, nullptr, P->dx, P->dsig, P->dg, P->dir, P->counter, st);
@@ -1569,64 +1716,56 @@ int wos_autotune(int d, int64_t M, int64_t Q, int64_t n_walks, const char* cache
     std::vector<float> hq((size_t)Q * kBatchStride, 0.f);
     for (int64_t q = 0; q < Q; ++q)
         for (int i = 0; i < d; ++i) hq[q * kBatchStride + i] = (float)((2 * rnd() - 1) * (pi - 0.05));
-    float *dq = nullptr, *du = nullptr, *dgr = nullptr, *dub = nullptr, *ddx = nullptr;
-    double *dds = nullptr, *ddg = nullptr;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
+    float* dq = nullptr;
     hipError_t e = hipMalloc(&dq, hq.size() * sizeof(float));
-    if (e == hipSuccess) e = hipMalloc(&du, Q * sizeof(float));
-    if (e == hipSuccess) e = hipMalloc(&dgr, Q * kBatchStride * sizeof(float));
-    if (e == hipSuccess) e = hipMalloc(&dub, Q * sizeof(float));
-    if (e == hipSuccess) e = hipMalloc(&ddx, Q * kBatchStride * sizeof(float));
-    if (e == hipSuccess) e = hipMalloc(&dds, sizeof(double));
-    if (e == hipSuccess) e = hipMalloc(&ddg, sizeof(double));
     if (e == hipSuccess) e = hipMemcpy(dq, hq.data(), hq.size() * sizeof(float), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = launch_fill_u32((unsigned*)dub, Q, 0x3f800000u, nullptr);
-    if (e == hipSuccess) e = hipEventCreate(&e0);
-    if (e == hipSuccess) e = hipEventCreate(&e1);
-    Tune best;
-    float best_ms = INFINITY;
-    const int upws[] = {1, 2, 4, 8, 16};
-    const int gms[] = {1, 2};
-    const int wpls[] = {1, 2, 4};
+    TuneRun run;
     const wos_domain* envs[1] = {D};
     const int64_t qoff[2] = {0, Q};
     const int64_t nw[1] = {n_walks};
     const double sig = 2.0, ep = 1e-4;
-    for (int wpl : wpls) {
-        for (int gm : gms) {
-        for (int upw : upws) {
-            if (e != hipSuccess || rc) break;
-            // warm-up then one timed launch
-            for (int rep = 0; rep < 2 && !rc && e == hipSuccess; ++rep) {
-                if (rep == 1) e = hipEventRecord(e0, nullptr);
-                const Tune force{upw, gm, wpl};
-                rc = run_batch(envs, 1, dq, qoff, &sig, &ep, nw, 1234 + rep, du, dgr, nullptr, dub, ddx, dds, ddg,
-                               nullptr, nullptr, &force, false);
-                if (rep == 1 && e == hipSuccess) e = hipEventRecord(e1, nullptr);
-            }
-            if (e == hipSuccess && !rc) e = hipEventSynchronize(e1);
-            float ms = 0;
-            if (e == hipSuccess && !rc) e = hipEventElapsedTime(&ms, e0, e1);
-            if (e == hipSuccess && !rc && ms < best_ms) {
-                best_ms = ms;
-                best = Tune{upw, gm, wpl};
-            }
-        }
-        }
-    }
-    if (e0) (void)hipEventDestroy(e0);
-    if (e1) (void)hipEventDestroy(e1);
-    void* bufs[] = {dq, du, dgr, dub, ddx, dds, ddg};
+    if (e == hipSuccess) rc = tune_batch(envs, 1, dq, qoff, &sig, &ep, nw, 1234, true, run);
     (void)hipDeviceSynchronize();
-    for (void* b : bufs)
-        if (b) (void)hipFree(b);
+    if (dq) (void)hipFree(dq);
     wos_destroy_domain(D);
-    if (rc) return rc;
     if (e != hipSuccess) return hip_fail(e, "autotune");
+    if (rc) return rc;
+    char k[48];
+    tune_key(k, d, M, Q);
     std::lock_guard<std::mutex> lk(g_tune_mu);
     if (!g_tune_loaded || g_tune_path != cache_path) load_tune_locked(cache_path);
-    g_tune[tune_key(d, M, Q)] = best;
+    g_tune[k] = run.best;
     return save_tune_locked(cache_path);
+}
+
+int wos_autotune_batch(const wos_domain* const* envs, int n_envs, const float* queries, const int64_t* q_offsets,
+                       const double* sigma, const double* eps, const int64_t* n_walks, uint64_t seed, int fused,
+                       const char* cache_path, wos_tune_result* out)
+{
+    if (n_envs < 1 || !envs || !queries || !q_offsets || !sigma || !eps || !n_walks)
+        return fail(WOS_EINVAL, "bad autotune arguments");
+    TuneRun run;
+    int rc = tune_batch(envs, n_envs, queries, q_offsets, sigma, eps, n_walks, seed, fused != 0, run);
+    if (rc) return rc;
+    char k[48];
+    mix_key(k, envs, q_offsets, n_envs, n_walks);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        if (cache_path && *cache_path && (!g_tune_loaded || g_tune_path != cache_path)) load_tune_locked(cache_path);
+        if (!g_tune_loaded) load_tune_locked(getenv("WOS_AUTOTUNE_CACHE"));
+        g_tune[k] = run.best;
+        if (cache_path && *cache_path && (rc = save_tune_locked(cache_path))) return rc;
+    }
+    if (out) {
+        out->waves_per_block = run.best.waves_per_block;
+        out->units_per_wave = run.best.units_per_wave;
+        out->grid_mult = run.best.grid_mult;
+        out->walks_per_lane = run.best.walks_per_lane;
+        out->ms_default = run.ms_default;
+        out->ms_best = run.ms_best;
+        out->tried = run.tried;
+    }
+    return WOS_OK;
 }
 
 }  // extern "C"

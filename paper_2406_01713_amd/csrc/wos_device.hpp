@@ -476,9 +476,18 @@ __device__ __forceinline__ float float_of_ord(uint32_t o)
     return __uint_as_float((o & 0x80000000u) ? (o & 0x7FFFFFFFu) : ~o);
 }
 
-// per-wave queue of (cluster << 6 | walker) entries and per-walker minima
-static __shared__ uint32_t g_pair_queue[kMaxWavesPerBlock][kPairCap];
-static __shared__ uint32_t g_pair_best[kMaxWavesPerBlock][kWave];
+// Obstacle distances evaluated, summed over the live lanes of a wave: the
+// scans are wave-uniform, so every lane evaluates the same rows, and the
+// tally is one wave-level count for the work statistics.  Callers run the
+// step on every lane of the wave (idle lanes with live false), so the tally
+// is updated in wave-uniform control flow.  pairs: the wave's LDS slice of
+// kPairLds words for the pair-compacted scan (kPairCap queue entries of
+// cluster << 6 | walker, then the 64 walkers' minima), owned by the kernel.
+struct WorkCount {
+    uint64_t sph = 0, box = 0;
+    uint32_t* pairs;
+    __device__ explicit WorkCount(uint32_t* p) : pairs(p) {}
+};
 
 // Evaluate queue entries [base, base + count), count <= 64, one per lane.
 // All lanes of the wave take part (the walker positions move by lane
@@ -528,9 +537,9 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v)
 
 // Min over the members of the clusters each lane may need (thr as for
 // cluster_min), with the cluster test on the matrix cores and the members
-// scanned pair by pair.  Requires every lane of the wave to be active and
-// blocks of at most kMaxWavesPerBlock waves.  evals: member distances
-// evaluated by the wave.
+// scanned pair by pair.  Requires every lane of the wave to be active; lds is
+// the wave's kPairLds-word slice (queue, then minima).  evals: member
+// distances evaluated by the wave.
 //
 // Per tile each lane gathers its 16 needs (bit 4 rt + r: walker 16 rt + 4 g +
 // r, g = lane / 16, needs cluster 16 t + lane % 16) into one mask; a wave
@@ -540,12 +549,12 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v)
 // (at most 4 x 64 pairs each).
 template <int D, bool BOX>
 __device__ __forceinline__ float cluster_min_pairs(cptr<float> rows, const float* __restrict__ mf, int n_cl,
-                                                   const float (&x)[D], float thr, bool live, uint64_t& evals)
+                                                   const float (&x)[D], float thr, bool live, uint64_t& evals,
+                                                   uint32_t* lds)
 {
     const int lane = threadIdx.x & (kWave - 1);
-    const int wv = (int)(threadIdx.x / kWave);
-    uint32_t* queue = g_pair_queue[wv];
-    uint32_t* best = g_pair_best[wv];
+    uint32_t* queue = lds;
+    uint32_t* best = lds + kPairCap;
     best[lane] = ord_of(Math<float>::inf());
     float A[3][4];
     mfma_walker_operands<D>(x, thr, live, A);
@@ -610,15 +619,6 @@ __device__ __forceinline__ float cluster_min_pairs(cptr<float> rows, const float
     return float_of_ord(best[lane]);
 }
 
-// Obstacle distances evaluated, summed over the live lanes of a wave: the
-// scans are wave-uniform, so every lane evaluates the same rows, and the
-// tally is one wave-level count for the work statistics.  Callers run the
-// step on every lane of the wave (idle lanes with live false), so the tally
-// is updated in wave-uniform control flow.
-struct WorkCount {
-    uint64_t sph, box;
-};
-
 // R = distance to the boundary; cls = first component attaining it in the
 // order goal, spheres, boxes, outer.  The goal and outer distances come first
 // and bound the box scan, whose result then bounds the sphere scan; culled
@@ -657,7 +657,7 @@ __device__ __forceinline__ T distance(cenv<T> p, const T (&x)[D], int& cls, Work
         if constexpr (sizeof(T) == 4) {
             if (p->use_mfma == 2) {
                 db = cluster_min_pairs<D, true>(to_const(p->box_cl), fresh(p)->box_mf, fresh(p)->n_cl_box, xg,
-                                                dga, live, eb);
+                                                dga, live, eb, wc.pairs);
                 done = true;
             } else if (p->use_mfma) {
                 db = cluster_min_mfma<D, true>(to_const(p->box_cl), fresh(p)->box_mf, fresh(p)->n_cl_box, xg,
@@ -680,7 +680,7 @@ __device__ __forceinline__ T distance(cenv<T> p, const T (&x)[D], int& cls, Work
         if constexpr (sizeof(T) == 4) {
             if (p->use_mfma == 2) {
                 ds = cluster_min_pairs<D, false>(to_const(p->sph_cl), fresh(p)->sph_mf, fresh(p)->n_cl_sph, xg,
-                                                 Math<T>::min(dga, db), live, es);
+                                                 Math<T>::min(dga, db), live, es, wc.pairs);
                 done = true;
             } else if (p->use_mfma) {
                 ds = cluster_min_mfma<D, false>(to_const(p->sph_cl), fresh(p)->sph_mf, fresh(p)->n_cl_sph, xg,

@@ -120,9 +120,10 @@ plain_kernel(const EnvP<T>* penv, const T* __restrict__ queries, int64_t n_units
              int64_t n_walks, int64_t w_base, uint32_t q_base, const uint64_t* __restrict__ key_add,
              double* __restrict__ partials, double* __restrict__ records)
 {
+    __shared__ uint32_t pair_lds[kBlock / kWave][kPairLds];
     const int lane = threadIdx.x & (kWave - 1);
-    const int64_t unit = (int64_t)blockIdx.x * (kBlock / kWave) +
-                         __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int64_t unit = (int64_t)blockIdx.x * (kBlock / kWave) + wv;
     if (unit >= n_units) return;
     const int64_t q = unit / chunks;
     const int64_t wi = (unit - q * chunks) * kWave + lane;
@@ -144,7 +145,7 @@ plain_kernel(const EnvP<T>* penv, const T* __restrict__ queries, int64_t n_units
     e.steps = 0;
     e.status = kTruncated;
     e.cls = kOuter;
-    WorkCount wc{0, 0};
+    WorkCount wc(pair_lds[wv]);
     // every lane steps until the wave's last walk ends (a finished lane runs
     // along idle), so the obstacle scans and the work tally stay wave-uniform
     bool done = !active;
@@ -314,7 +315,7 @@ constexpr int kLdsAcc = 2 * kMaxDim;
 // code.  Accumulators other than the gradient ones stay in registers.
 template <bool BWD, bool SRC>
 __device__ __forceinline__ void run_unit(cenv<float> p, CBatch& be, int64_t local, const float* queries,
-                                         uint32_t k0, uint32_t k1, double* lds, double* out)
+                                         uint32_t k0, uint32_t k1, double* lds, uint32_t* pairs, double* out)
 {
     const int lane = threadIdx.x & (kWave - 1);
     const int d = be.d;
@@ -346,7 +347,7 @@ __device__ __forceinline__ void run_unit(cenv<float> p, CBatch& be, int64_t loca
     walker_start<float, kMaxDim, kMaxDim>(s, xq, (uint32_t)next);
     int64_t base = w_begin + kWave;
     const uint32_t qi = (uint32_t)ql;
-    WorkCount wc{0, 0};
+    WorkCount wc(pairs);
 
     while (__any(active)) {
         WalkEnd<float> e;
@@ -405,21 +406,22 @@ __device__ __forceinline__ void run_unit(cenv<float> p, CBatch& be, int64_t loca
     wave_store<kNAccBatch>(row, out);
 }
 
-// 4 waves per SIMD: the register allocator then spills about 100 bytes per lane
-// of rarely used state, which measured faster than 3 waves without spills.
-#ifndef WOS_PERSISTENT_MIN_WAVES
-#define WOS_PERSISTENT_MIN_WAVES 4
-#endif
-
-template <bool BWD, bool SRC>
-__global__ void __launch_bounds__(kBlock, WOS_PERSISTENT_MIN_WAVES)
+// Launch shape: WPB waves per block (1, 2 or 4; the LDS slices scale with
+// it) and at least 4 resident waves per SIMD in every shape (the second
+// launch bound: at most 128 registers per lane).  4 waves per SIMD measured
+// faster than 3 (6 %) or 5 (18 %, spills).
+template <bool BWD, bool SRC, int WPB>
+__global__ void __launch_bounds__(WPB * kWave, 4)
 persistent_kernel(const EnvP<float>* envs, const BatchEnv* benv, int n_benv,
                   const float* __restrict__ queries, int64_t total_units,
                   uint32_t key0, uint32_t key1, const uint64_t* __restrict__ key_add,
                   unsigned* counter, double* __restrict__ partials)
 {
-    __shared__ double lds_acc[kBlock / kWave][kLdsAcc * kWave];
-    double* lds = lds_acc[threadIdx.x / kWave];
+    __shared__ double lds_acc[WPB][kLdsAcc * kWave];
+    __shared__ uint32_t pair_lds[WPB][kPairLds];
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    double* lds = lds_acc[wv];
+    uint32_t* pairs = pair_lds[wv];
     uint32_t k0 = key0, k1 = key1;
     apply_key_add(k0, k1, key_add);
     CBatch* B = (CBatch*)benv;
@@ -440,7 +442,8 @@ persistent_kernel(const EnvP<float>* envs, const BatchEnv* benv, int n_benv,
         }
         CBatch& be = B[lo];
         const cenv<float> p = (cenv<float>)(envs + be.slot);
-        run_unit<BWD, SRC>(p, be, (int64_t)u - be.unit_off, queries, k0, k1, lds, partials + (int64_t)u * kNAccBatch);
+        run_unit<BWD, SRC>(p, be, (int64_t)u - be.unit_off, queries, k0, k1, lds, pairs,
+                           partials + (int64_t)u * kNAccBatch);
     }
 }
 
@@ -549,6 +552,7 @@ plan_update(const EnvP<float>* penv, float* __restrict__ x, int64_t n, const flo
             int grad_stride, float s_ub, double* __restrict__ path_len, int32_t* __restrict__ stalls,
             int32_t* __restrict__ status, uint64_t* step)
 {
+    __shared__ uint32_t pair_lds[kBlock / kWave][kPairLds];
     const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const cenv<float> p = (cenv<float>)penv;
     // every lane evaluates the distance (the matrix-core cluster test needs
@@ -559,7 +563,7 @@ plan_update(const EnvP<float>* penv, float* __restrict__ x, int64_t n, const flo
 #pragma unroll
     for (int i = 0; i < D; ++i) xs[i] = (n > 0) ? x[si * D + i] : 0.0f;
     int cls;
-    WorkCount wc{0, 0};
+    WorkCount wc(pair_lds[__builtin_amdgcn_readfirstlane(threadIdx.x / kWave)]);
     const float R = distance<float, D>(p, xs, cls, wc, valid);
     if (valid) {
         float dz2 = 0.0f;
@@ -732,12 +736,22 @@ hipError_t launch_reduce_pairs(const double* prod, int64_t n, double* out0, doub
 }
 
 template <bool BWD, bool SRC>
-static void persistent_go(int grid, int block, const EnvP<float>* envs, const BatchEnv* benv, int n_benv,
-                          const float* queries, int64_t total_units, uint32_t key0, uint32_t key1,
-                          const uint64_t* key_add, unsigned* counter, double* partials, hipStream_t st)
+static hipError_t persistent_go(int grid, int block, const EnvP<float>* envs, const BatchEnv* benv, int n_benv,
+                                const float* queries, int64_t total_units, uint32_t key0, uint32_t key1,
+                                const uint64_t* key_add, unsigned* counter, double* partials, hipStream_t st)
 {
-    hipLaunchKernelGGL((persistent_kernel<BWD, SRC>), dim3(grid), dim3(block), 0, st, envs, benv, n_benv, queries,
-                       total_units, key0, key1, key_add, counter, partials);
+#define WOS_PERSISTENT_CASE(W)                                                                                  \
+    case W * kWave:                                                                                             \
+        hipLaunchKernelGGL((persistent_kernel<BWD, SRC, W>), dim3(grid), dim3(block), 0, st, envs, benv, n_benv, \
+                           queries, total_units, key0, key1, key_add, counter, partials);                       \
+        return hipSuccess;
+    switch (block) {
+        WOS_PERSISTENT_CASE(1)
+        WOS_PERSISTENT_CASE(2)
+        WOS_PERSISTENT_CASE(4)
+    default: return hipErrorInvalidValue;
+    }
+#undef WOS_PERSISTENT_CASE
 }
 
 hipError_t launch_persistent(bool bwd, bool src, int grid, int block, const EnvP<float>* envs,
@@ -746,27 +760,38 @@ hipError_t launch_persistent(bool bwd, bool src, int grid, int block, const EnvP
                              double* partials, hipStream_t st)
 {
     if (total_units == 0) return hipSuccess;
-    if (block != kBlock) return hipErrorInvalidValue;
+    hipError_t e;
     if (bwd && src)
-        persistent_go<true, true>(grid, block, envs, benv, n_benv, queries, total_units, key0, key1, key_add, counter, partials, st);
+        e = persistent_go<true, true>(grid, block, envs, benv, n_benv, queries, total_units, key0, key1, key_add, counter, partials, st);
     else if (bwd)
-        persistent_go<true, false>(grid, block, envs, benv, n_benv, queries, total_units, key0, key1, key_add, counter, partials, st);
+        e = persistent_go<true, false>(grid, block, envs, benv, n_benv, queries, total_units, key0, key1, key_add, counter, partials, st);
     else if (src)
-        persistent_go<false, true>(grid, block, envs, benv, n_benv, queries, total_units, key0, key1, key_add, counter, partials, st);
+        e = persistent_go<false, true>(grid, block, envs, benv, n_benv, queries, total_units, key0, key1, key_add, counter, partials, st);
     else
-        persistent_go<false, false>(grid, block, envs, benv, n_benv, queries, total_units, key0, key1, key_add, counter, partials, st);
-    return hipGetLastError();
+        e = persistent_go<false, false>(grid, block, envs, benv, n_benv, queries, total_units, key0, key1, key_add, counter, partials, st);
+    return e != hipSuccess ? e : hipGetLastError();
+}
+
+template <bool BWD, bool SRC>
+static int resident_per_cu(int block)
+{
+    int per_cu = 0;
+    hipError_t e = hipErrorInvalidValue;
+    switch (block) {
+    case 1 * kWave: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persistent_kernel<BWD, SRC, 1>, block, 0); break;
+    case 2 * kWave: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persistent_kernel<BWD, SRC, 2>, block, 0); break;
+    case 4 * kWave: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persistent_kernel<BWD, SRC, 4>, block, 0); break;
+    default: break;
+    }
+    return (e == hipSuccess && per_cu > 0) ? per_cu : 1;
 }
 
 int persistent_resident_blocks(bool bwd, bool src, int block)
 {
-    int per_cu = 0;
-    hipError_t e;
-    if (bwd && src) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persistent_kernel<true, true>, block, 0);
-    else if (bwd) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persistent_kernel<true, false>, block, 0);
-    else if (src) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persistent_kernel<false, true>, block, 0);
-    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persistent_kernel<false, false>, block, 0);
-    if (e != hipSuccess || per_cu < 1) per_cu = 1;
+    const int per_cu = (bwd && src) ? resident_per_cu<true, true>(block)
+                       : bwd        ? resident_per_cu<true, false>(block)
+                       : src        ? resident_per_cu<false, true>(block)
+                                    : resident_per_cu<false, false>(block);
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess) return per_cu;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 1;

@@ -50,7 +50,7 @@ constexpr int kClusterMin = 64;
 // one pass when they fit, else one row tile (at most 256) at a time after
 // the waiting ones are evaluated, so 320 entries never overflow.
 constexpr int kPairCap = 320;
-constexpr int kMaxWavesPerBlock = 4;  // every walk kernel runs <= 256 threads per block
+constexpr int kPairLds = kPairCap + kWave;  // pair-scan LDS words per wave: queue, then minima
 
 constexpr int kMfmaTile = 16;
 constexpr int kMfmaFeat = 12;

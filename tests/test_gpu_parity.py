@@ -670,13 +670,66 @@ def test_autotune_writes_cache_and_batch_uses_it(B):
         path = os.path.join(td, "tune.json")
         B.wos_autotune(7, 64, 32, 256, path)
         txt = open(path).read()
-        assert "units_per_wave" in txt and "walks_per_lane" in txt and "d7_" in txt
+        assert "units_per_wave" in txt and "walks_per_lane" in txt and "waves_per_block" in txt and "d7_" in txt
         B.wos_set_autotune_cache(path)
         envs = _ragged(n_envs=3, q_cap=8, n_walks=256)
         a = gpu_batch(B, envs, 256, 5)
         B.wos_set_autotune_cache(None)
         b = gpu_batch(B, envs, 256, 5)
         assert np.allclose(a["u"], b["u"], rtol=2e-5, atol=1e-7)
+
+
+def _batch_args(B, envs):
+    import torch
+    Qs = [len(e["queries"]) for e in envs]
+    off = np.concatenate([[0], np.cumsum(Qs)]).astype(np.int64)
+    qp = np.zeros((off[-1], 8), dtype=np.float32)
+    for e, s in enumerate(envs):
+        qp[off[e]:off[e + 1], :s["d"]] = s["queries"]
+    return [B.Domain(e) for e in envs], dev(qp, torch.float32), off
+
+
+def test_autotune_batch_and_every_block_shape(B):
+    """The batch tuner times launch shapes on the caller's own batch and
+    records the best under the batch's mix key; every block shape (1, 2 and 4
+    waves per block), with other unit and walk-range splits, gives the same
+    walks as the built-in shape (identical step and degenerate counts, means
+    equal up to summation order)."""
+    import json
+    envs = _ragged(n_envs=6, q_cap=24, n_walks=512)
+    rng = np.random.default_rng(4)
+    ubar = rng.normal(size=sum(len(e["queries"]) for e in envs)).astype(np.float32)
+    B.wos_set_autotune_cache(None)
+    ref = gpu_batch(B, envs, 512, 5, ubar=ubar)
+    doms, q, off = _batch_args(B, envs)
+    with tempfile.TemporaryDirectory() as td:
+        path = os.path.join(td, "tune.json")
+        r = B.wos_autotune_batch(doms, q, off, [e["sigma"] for e in envs], [e["eps"] for e in envs], 512, 5,
+                                 fused=True, cache_path=path)
+        print("tuned shape:", r)
+        assert r["waves_per_block"] in (1, 2, 4) and r["units_per_wave"] in (1, 2, 4, 8, 16)
+        assert r["grid_mult"] in (1, 2) and r["walks_per_lane"] in (1, 2, 4)
+        assert 0 < r["ms_best"] <= r["ms_default"] and r["tried"] >= 9
+        cache = json.load(open(path))
+        keys = [k for k in cache if k.startswith("mix_6_")]
+        assert len(keys) == 1
+        key = keys[0]
+        order = ("units_per_wave", "grid_mult", "walks_per_lane", "waves_per_block")  # the file's key order
+        for shape in ({"waves_per_block": 1, "units_per_wave": 2, "grid_mult": 1, "walks_per_lane": 1},
+                      {"waves_per_block": 2, "units_per_wave": 8, "grid_mult": 2, "walks_per_lane": 4},
+                      {"waves_per_block": 4, "units_per_wave": 1, "grid_mult": 2, "walks_per_lane": 2},
+                      cache[key]):
+            with open(path, "w") as f:
+                f.write("{\n  \"%s\": %s\n}\n" % (key, json.dumps({k: shape[k] for k in order})))
+            B.wos_set_autotune_cache(path)
+            out = gpu_batch(B, envs, 512, 5, ubar=ubar)
+            for k in ("u", "g", "dx"):
+                assert np.allclose(out[k], ref[k], rtol=1e-5, atol=1e-7), (shape, k)
+            assert np.allclose(out["ds"], ref["ds"], rtol=1e-5, atol=1e-9) and np.allclose(out["dg"], ref["dg"],
+                                                                                            rtol=1e-5, atol=1e-9)
+            assert np.array_equal(out["st"][:, 9], ref["st"][:, 9]), shape   # same walks: same step counts
+            assert np.array_equal(out["st"][:, 10:12], ref["st"][:, 10:12]), shape
+    B.wos_set_autotune_cache(None)
 
 
 # ------------------------------------------------------------ planning ----
