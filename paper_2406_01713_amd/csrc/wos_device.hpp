@@ -500,7 +500,10 @@ __device__ __forceinline__ void pair_round(cptr<float> rows, int n_cl, const uin
     const int lane = threadIdx.x & (kWave - 1);
     const bool act = lane < count;
     const uint32_t e = act ? queue[base + lane] : 0u;
-    const int w = (int)(e & (kWave - 1));
+    // walker field q = 16 rt + 4 r + g (see cluster_min_pairs) -> the walker's
+    // lane 16 rt + 4 g + r
+    const uint32_t q = e & (kWave - 1);
+    const int w = (int)((q & 0x30u) | ((q & 3u) << 2) | ((q >> 2) & 3u));
     int c = (int)(e >> 6);
     c = c < n_cl ? c : n_cl - 1;  // an entry never points past the table
     float xw[D];
@@ -560,14 +563,20 @@ __device__ __forceinline__ float cluster_min_pairs(cptr<float> rows, const float
     mfma_walker_operands<D>(x, thr, live, A);
     const mf4* tab = reinterpret_cast<const mf4*>(mf) + lane;
     const int n_tiles = (n_cl + kMfmaTile - 1) / kMfmaTile;
-    // queue entry: cluster << 6 | walker; the lane's own part of both
-    const uint32_t lane_e = ((uint32_t)(lane & (kMfmaTile - 1)) << 6) | (4u * (uint32_t)(lane >> 4));
+    // queue entry: cluster << 6 | q, where the need bit 4 rt + r of lane
+    // 16 g + j (walker 16 rt + 4 g + r, cluster 16 t + j) gives
+    // q = (bit << 2) | g = 16 rt + 4 r + g, so each entry is one shift-or of
+    // the bit index into the lane's constant part
+    const uint32_t lane_e = ((uint32_t)(lane & (kMfmaTile - 1)) << 6) | (uint32_t)(lane >> 4);
     int qn = 0;  // queued pairs (wave-uniform), < 64 between tiles
     uint32_t pairs = 0;
     for (int t = 0; t < n_tiles; ++t) {
         const mf4 b = tab[t * kWave];
-        // bits shift in from the top (rt = 3, r = 3 first), so no bit
-        // constants are needed
+        // need bit = the test value's sign bit, shifted in from the top
+        // (rt = 3, r = 3 first) with one v_alignbit per value: a value >= +0
+        // is skipped, which the margin makes as sound as > 0 (the rounding is
+        // far below m times the sum of squares); NaN (a non-finite walker)
+        // with the sign clear skips too
         uint32_t nm = 0;
 #pragma unroll
         for (int rt = 3; rt >= 0; --rt) {
@@ -576,7 +585,7 @@ __device__ __forceinline__ float cluster_min_pairs(cptr<float> rows, const float
             acc = __builtin_amdgcn_mfma_f32_16x16x4f32(A[1][rt], b[1], acc, 0, 0, 0);
             acc = __builtin_amdgcn_mfma_f32_16x16x4f32(A[2][rt], b[2], acc, 0, 0, 0);
 #pragma unroll
-            for (int r = 3; r >= 0; --r) nm = nm + nm + (uint32_t)!(acc[r] > 0.0f);  // NaN never skips
+            for (int r = 3; r >= 0; --r) nm = __builtin_amdgcn_alignbit(nm, __float_as_uint(acc[r]), 31u);
         }
         uint32_t cnt = (uint32_t)__builtin_popcount(nm);
         uint32_t incl = wave_incl_scan(cnt);
@@ -602,7 +611,7 @@ __device__ __forceinline__ float cluster_min_pairs(cptr<float> rows, const float
             while (m) {  // per lane: its own needs, in bit order
                 const uint32_t bit = (uint32_t)__builtin_ctz(m);
                 m &= m - 1u;
-                queue[pos++] = (tile_e + lane_e) | (16u * (bit >> 2) + (bit & 3u));
+                queue[pos++] = (bit << 2) | (tile_e + lane_e);
             }
             qn += total;
             while (qn >= kWave) {  // the last 64 queued go first

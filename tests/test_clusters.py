@@ -255,10 +255,11 @@ def _far_tight_sets():
 
 @pytest.mark.parametrize("order", ["fma", "reverse", "pairs"])
 def test_matrix_core_cull_test_is_sound_in_fp32(B, order):
-    """Wherever the matrix-core test skips a cluster for a walker (feature
-    dot product > 0, computed in FP32 in any of three rounding orders), every
-    member's FP32 distance exceeds the walker's threshold: thresholds are put
-    at, just below and just above the exact bound, the hardest cases."""
+    """Wherever the matrix-core test skips a cluster for a walker (the FP32
+    feature dot product, in any of three rounding orders, has its sign bit
+    clear: +0 included, since the margin dwarfs the rounding), every member's
+    FP32 distance exceeds the walker's threshold: thresholds are put at, just
+    below and just above the exact bound, the hardest cases."""
     rng = np.random.default_rng(11)
     for name, s in _sets() + _far_tight_sets():
         d = s["d"]
@@ -289,7 +290,7 @@ def test_matrix_core_cull_test_is_sound_in_fp32(B, order):
                 thr = np.maximum(exact_lb[np.arange(len(x)), g] * (1 + rel), 1e-6).astype(np.float32)
                 a, b = _mfma_features(x, thr, bc, br, d)
                 D = _dot32(a, b, order)
-                skip = D > 0
+                skip = ~np.signbit(D)
                 bad = skip & ~(member_min > thr[:, None])
                 assert not bad.any(), (name, kind, rel, np.argwhere(bad)[:3])
                 checked += skip.sum()
