@@ -85,10 +85,12 @@ struct Math<float> {
         s = __builtin_amdgcn_sinf(t);
         c = __builtin_amdgcn_cosf(t);
     }
-    // (2 (x >> 9) + 1) 2^-24: exact in FP32
+    // (2 (x >> 9) + 1) 2^-24: the bits 0x3F800000 | (x >> 9) (one v_alignbit
+    // of 0x7F:x) are 1 + (x >> 9) 2^-23, and subtracting 1 - 2^-24 is exact
+    // (Sterbenz: both lie in [1/2, 2])
     static __device__ __forceinline__ float uniform(uint32_t x)
     {
-        return (float)(2u * (x >> 9) + 1u) * 0x1p-24f;
+        return __uint_as_float(__builtin_amdgcn_alignbit(0x7Fu, x, 9u)) - 0x1.fffffep-1f;
     }
 };
 
@@ -838,12 +840,22 @@ __device__ __forceinline__ T boundary_value(cenv<T> p, const T (&x)[D], int cls)
     return p->mode == 1 ? s + p->b : Math<T>::exp(s);
 }
 
-// 0F1(; b; y) by Horner's rule on the host-computed coefficients.
+// 0F1(; b; y) by Horner's rule on the host-computed coefficients, four
+// terms per iteration (one 16-byte scalar load).  The tables are zero beyond
+// nt and hold kMaxTerms (a multiple of 4) entries, so the sum starts at up to
+// three zero coefficients above the top term: fma(0, y, c) = c exactly, and
+// the value is bit for bit that of a loop over nt terms.
+static_assert(kMaxTerms % 4 == 0, "Horner tables are read four terms at a time");
 template <typename T, typename C>
 __device__ __forceinline__ T horner(const C& c, int nt, T y)
 {
-    T acc = c[nt - 1];
-    for (int i = nt - 2; i >= 0; --i) acc = Math<T>::fma(acc, y, c[i]);
+    T acc = T(0);
+    for (int i = ((nt + 3) & ~3) - 4; i >= 0; i -= 4) {
+        acc = Math<T>::fma(acc, y, c[i + 3]);
+        acc = Math<T>::fma(acc, y, c[i + 2]);
+        acc = Math<T>::fma(acc, y, c[i + 1]);
+        acc = Math<T>::fma(acc, y, c[i]);
+    }
     return acc;
 }
 
@@ -1107,9 +1119,9 @@ __device__ __forceinline__ bool walker_step(cenv<T> p0, Walker<T, DA>& s, uint32
     if (BWD) {
         const T p1 = horner<T>(p->cC1, p->nt_C1, y);
         s.S = Math<T>::fma(T(-0.5 / D) * R2 * p1, C, s.S);
-        if (k == 0) s.gfac = (T(D) / R) * Math<T>::rcp(p1);
+        if (k == 0) s.gfac = T(D) * Math<T>::rcp(R * p1);
     } else if (k == 0) {
-        s.gfac = (T(D) / R) * Math<T>::rcp(horner<T>(p->cC1, p->nt_C1, y));
+        s.gfac = T(D) * Math<T>::rcp(R * horner<T>(p->cC1, p->nt_C1, y));
     }
     T v[D];
     direction<T, D>(k, s.w, q, fresh(p0)->env_id, key0, key1, v);
