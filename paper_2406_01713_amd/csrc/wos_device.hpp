@@ -572,8 +572,12 @@ __device__ __forceinline__ float cluster_min_pairs(cptr<float> rows, const float
     const uint32_t lane_e = ((uint32_t)(lane & (kMfmaTile - 1)) << 6) | (uint32_t)(lane >> 4);
     int qn = 0;  // queued pairs (wave-uniform), < 64 between tiles
     uint32_t pairs = 0;
+    // the next tile's features load while this tile is tested and queued (the
+    // table ends with a spare tile that is never used)
+    mf4 bn = tab[0];
     for (int t = 0; t < n_tiles; ++t) {
-        const mf4 b = tab[t * kWave];
+        const mf4 b = bn;
+        bn = tab[(t + 1) * kWave];
         // need bit = the test value's sign bit, shifted in from the top
         // (rt = 3, r = 3 first) with one v_alignbit per value: a value >= +0
         // is skipped, which the margin makes as sound as > 0 (the rounding is
