@@ -79,8 +79,8 @@ class Options(C.Structure):
 
 class TuneResult(C.Structure):
     _fields_ = [("waves_per_block", C.c_int), ("units_per_wave", C.c_int), ("grid_mult", C.c_int),
-                ("walks_per_lane", C.c_int), ("ms_default", C.c_double), ("ms_best", C.c_double),
-                ("tried", C.c_int)]
+                ("walks_per_lane", C.c_int), ("lanes_per_walker", C.c_int), ("ms_default", C.c_double),
+                ("ms_best", C.c_double), ("tried", C.c_int)]
 
 
 def _load():

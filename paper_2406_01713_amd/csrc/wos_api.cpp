@@ -570,6 +570,7 @@ struct Tune {
     int grid_mult = 1;
     int walks_per_lane = 2;   // least walks per lane in a work unit (lane refill needs 2)
     int waves_per_block = 4;  // block of 64, 128 or 256 threads
+    int lanes_per_walker = 1; // 64 / walks a wave carries at once (1, 2, 4, ..., 64)
 };
 std::mutex g_tune_mu;
 std::map<std::string, Tune, std::less<>> g_tune;  // transparent: lookups by char* allocate nothing
@@ -603,7 +604,8 @@ bool valid_tune(const Tune& t)
 {
     return t.units_per_wave > 0 && t.units_per_wave <= 64 && t.grid_mult > 0 && t.grid_mult <= 8 &&
            t.walks_per_lane > 0 && t.walks_per_lane <= 64 &&
-           (t.waves_per_block == 1 || t.waves_per_block == 2 || t.waves_per_block == 4);
+           (t.waves_per_block == 1 || t.waves_per_block == 2 || t.waves_per_block == 4) &&
+           t.lanes_per_walker > 0 && t.lanes_per_walker <= kWave && (t.lanes_per_walker & (t.lanes_per_walker - 1)) == 0;
 }
 
 void load_tune_locked(const char* path)
@@ -619,14 +621,16 @@ void load_tune_locked(const char* path)
         char key[64];
         Tune t;
         // one entry per line: "key": {"units_per_wave": U, "grid_mult": G,
-        // "walks_per_lane": W, "waves_per_block": B}, (W, B absent in older
-        // files: 2, 4)
+        // "walks_per_lane": W, "waves_per_block": B, "lanes_per_walker": L}
+        // (W, B, L absent in older files: 2, 4, 1)
         const int n = sscanf(line,
                              " \"%63[^\"]\": {\"units_per_wave\": %d, \"grid_mult\": %d, \"walks_per_lane\": %d, "
-                             "\"waves_per_block\": %d}",
-                             key, &t.units_per_wave, &t.grid_mult, &t.walks_per_lane, &t.waves_per_block);
+                             "\"waves_per_block\": %d, \"lanes_per_walker\": %d}",
+                             key, &t.units_per_wave, &t.grid_mult, &t.walks_per_lane, &t.waves_per_block,
+                             &t.lanes_per_walker);
         if (n < 4) t.walks_per_lane = 2;
         if (n < 5) t.waves_per_block = 4;
+        if (n < 6) t.lanes_per_walker = 1;
         if (n >= 3 && valid_tune(t)) g_tune[key] = t;
     }
     fclose(f);
@@ -654,9 +658,9 @@ int save_tune_locked(const char* path)
     size_t i = 0;
     for (auto& kv : g_tune) {
         fprintf(f, "  \"%s\": {\"units_per_wave\": %d, \"grid_mult\": %d, \"walks_per_lane\": %d, "
-                   "\"waves_per_block\": %d}%s\n",
+                   "\"waves_per_block\": %d, \"lanes_per_walker\": %d}%s\n",
                 kv.first.c_str(), kv.second.units_per_wave, kv.second.grid_mult, kv.second.walks_per_lane,
-                kv.second.waves_per_block, (++i < g_tune.size()) ? "," : "");
+                kv.second.waves_per_block, kv.second.lanes_per_walker, (++i < g_tune.size()) ? "," : "");
     }
     fprintf(f, "}\n");
     fclose(f);
@@ -728,6 +732,10 @@ void plan_batch(const wos_domain* const* envs, const int64_t* q_off, int n_envs,
     if (force && force->grid_mult > 0) t.grid_mult = force->grid_mult;
     if (force && force->walks_per_lane > 0) t.walks_per_lane = force->walks_per_lane;
     if (force && force->waves_per_block > 0) t.waves_per_block = force->waves_per_block;
+    if (force && force->lanes_per_walker > 0) t.lanes_per_walker = force->lanes_per_walker;
+    // walks a wave carries at once; the other lanes only share the member
+    // scans of those walks (the pair rounds spread over all 64 lanes)
+    const int64_t lanes = kWave / t.lanes_per_walker;
     const int block = t.waves_per_block * kWave;
     const int resident_blocks = persistent_resident_blocks(true, src, block);
     L.block = block;
@@ -735,17 +743,18 @@ void plan_batch(const wos_domain* const* envs, const int64_t* q_off, int n_envs,
     const int64_t waves = (int64_t)L.grid * (block / kWave);
     const int64_t target = waves * t.units_per_wave;
     // one walk-range length for the launch: total walks / target units, a
-    // multiple of the wave width, at least walks_per_lane walks per lane
+    // multiple of the walk-carrying lanes, at least walks_per_lane walks per
+    // such lane
     // (default 2, so lanes refill).  Measured: on the 7-D planning step
     // (524288 walks, 4096 resident waves) 2 per lane beat 4 by 25 % (half the
     // waves had been idle) and 1 by 7 %; on one-start planning with 1e5 walks
     // 2 beat 1 by 5-20 % (a wave with one walk per lane waits for its longest
     // of 64 walks).
-    int64_t wps = std::max<int64_t>((int64_t)t.walks_per_lane * kWave, sumQW / std::max<int64_t>(target, 1));
+    int64_t wps = std::max<int64_t>((int64_t)t.walks_per_lane * lanes, sumQW / std::max<int64_t>(target, 1));
     wps = std::min(wps, maxW);
-    wps = ((wps + kWave - 1) / kWave) * kWave;
+    wps = ((wps + lanes - 1) / lanes) * lanes;
 
-    auto env_wps = [&](int e) { return std::min<int64_t>(wps, ((n_walks[e] + kWave - 1) / kWave) * kWave); };
+    auto env_wps = [&](int e) { return std::min<int64_t>(wps, ((n_walks[e] + lanes - 1) / lanes) * lanes); };
     auto cost = [&](int e) {
         return q_off[e + 1] > q_off[e] ? unit_cost(envs[e], env_wps(e)) : -1.0;
     };
@@ -771,7 +780,7 @@ void plan_batch(const wos_domain* const* envs, const int64_t* q_off, int n_envs,
         b.q_stride = q_stride;
         b.slot = e;
         b.n_cl = full_scan ? 0 : envs[e]->n_cl_sph + envs[e]->n_cl_box;
-        b.pad = 0;
+        b.lanes = (int32_t)lanes;
         b.unit_off = uoff;
         uoff += (int64_t)b.n_q * splits;
     }
@@ -995,18 +1004,23 @@ int tune_batch(const wos_domain* const* envs, int n_envs, const float* queries, 
     std::vector<std::pair<Tune, double>> seen{{cur, best_ms}};
     auto same = [](const Tune& a, const Tune& b) {
         return a.units_per_wave == b.units_per_wave && a.grid_mult == b.grid_mult &&
-               a.walks_per_lane == b.walks_per_lane && a.waves_per_block == b.waves_per_block;
+               a.walks_per_lane == b.walks_per_lane && a.waves_per_block == b.waves_per_block &&
+               a.lanes_per_walker == b.lanes_per_walker;
     };
-    static const int wpbs[] = {1, 2, 4}, upws[] = {1, 2, 4, 8, 16}, gms[] = {1, 2}, wpls[] = {1, 2, 4};
+    static const int wpbs[] = {1, 2, 4}, upws[] = {1, 2, 4, 8, 16}, gms[] = {1, 2}, wpls[] = {1, 2, 4},
+                     lpws[] = {1, 2, 4};
+    static const int* const vals_of[] = {wpbs, upws, gms, wpls, lpws};
+    static const int n_of[] = {3, 5, 2, 3, 3};
+    auto field = [](Tune& t, int prm) -> int& {
+        return prm == 0 ? t.waves_per_block : prm == 1 ? t.units_per_wave : prm == 2 ? t.grid_mult
+                                                       : prm == 3 ? t.walks_per_lane : t.lanes_per_walker;
+    };
     for (int pass = 0; pass < 2 && e == hipSuccess && !rc; ++pass) {
         bool moved = false;
-        for (int prm = 0; prm < 4; ++prm) {
-            const int* vals = prm == 0 ? wpbs : prm == 1 ? upws : prm == 2 ? gms : wpls;
-            const int nv = prm == 0 ? 3 : prm == 1 ? 5 : prm == 2 ? 2 : 3;
-            for (int i = 0; i < nv && e == hipSuccess && !rc; ++i) {
+        for (int prm = 0; prm < 5; ++prm) {
+            for (int i = 0; i < n_of[prm] && e == hipSuccess && !rc; ++i) {
                 Tune c = cur;
-                (prm == 0 ? c.waves_per_block : prm == 1 ? c.units_per_wave : prm == 2 ? c.grid_mult
-                                                                                        : c.walks_per_lane) = vals[i];
+                field(c, prm) = vals_of[prm][i];
                 double m = -1.0;
                 for (auto& s : seen)
                     if (same(s.first, c)) m = s.second;
@@ -1761,6 +1775,7 @@ int wos_autotune_batch(const wos_domain* const* envs, int n_envs, const float* q
         out->units_per_wave = run.best.units_per_wave;
         out->grid_mult = run.best.grid_mult;
         out->walks_per_lane = run.best.walks_per_lane;
+        out->lanes_per_walker = run.best.lanes_per_walker;
         out->ms_default = run.ms_default;
         out->ms_best = run.ms_best;
         out->tried = run.tried;

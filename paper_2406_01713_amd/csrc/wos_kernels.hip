@@ -341,11 +341,14 @@ __device__ __forceinline__ void run_unit(cenv<float> p, CBatch& be, int64_t loca
 #pragma unroll
     for (int i = 0; i < kLdsAcc; ++i) g[i * kWave] = 0.0;
 
+    // lanes [0, be.lanes) carry walks; the rest (with more than one lane per
+    // walker) only take part in the member scans of the pair rounds
+    const int lanes = be.lanes;
     Walker<float, kMaxDim> s;
     int64_t next = w_begin + lane;
-    bool active = next < w_end;
+    bool active = lane < lanes && next < w_end;
     walker_start<float, kMaxDim, kMaxDim>(s, xq, (uint32_t)next);
-    int64_t base = w_begin + kWave;
+    int64_t base = w_begin + lanes;
     const uint32_t qi = (uint32_t)ql;
     WorkCount wc(pairs);
 

@@ -112,7 +112,7 @@ struct BatchEnv {
     int32_t q_stride;   // row stride of the query array (elements)
     int32_t slot;       // position of the env in the caller's env array
     int32_t n_cl;       // cluster bounds evaluated per walk-step (spheres + boxes)
-    int32_t pad;
+    int32_t lanes;      // lanes of a wave that carry walks (64 / lanes per walker)
 };
 
 // Accumulator layout of one work unit's partial sums (doubles):

@@ -692,8 +692,8 @@ def _batch_args(B, envs):
 def test_autotune_batch_and_every_block_shape(B):
     """The batch tuner times launch shapes on the caller's own batch and
     records the best under the batch's mix key; every block shape (1, 2 and 4
-    waves per block), with other unit and walk-range splits, gives the same
-    walks as the built-in shape (identical step and degenerate counts, means
+    waves per block), with other unit and walk-range splits and 1, 2, 4 or 64
+    lanes per walker, gives the same walks as the built-in shape (identical step and degenerate counts, means
     equal up to summation order)."""
     import json
     envs = _ragged(n_envs=6, q_cap=24, n_walks=512)
@@ -708,16 +708,22 @@ def test_autotune_batch_and_every_block_shape(B):
                                  fused=True, cache_path=path)
         print("tuned shape:", r)
         assert r["waves_per_block"] in (1, 2, 4) and r["units_per_wave"] in (1, 2, 4, 8, 16)
-        assert r["grid_mult"] in (1, 2) and r["walks_per_lane"] in (1, 2, 4)
-        assert 0 < r["ms_best"] <= r["ms_default"] and r["tried"] >= 9
+        assert r["grid_mult"] in (1, 2) and r["walks_per_lane"] in (1, 2, 4) and r["lanes_per_walker"] in (1, 2, 4)
+        assert 0 < r["ms_best"] <= r["ms_default"] and r["tried"] >= 11
         cache = json.load(open(path))
         keys = [k for k in cache if k.startswith("mix_6_")]
         assert len(keys) == 1
         key = keys[0]
-        order = ("units_per_wave", "grid_mult", "walks_per_lane", "waves_per_block")  # the file's key order
-        for shape in ({"waves_per_block": 1, "units_per_wave": 2, "grid_mult": 1, "walks_per_lane": 1},
-                      {"waves_per_block": 2, "units_per_wave": 8, "grid_mult": 2, "walks_per_lane": 4},
-                      {"waves_per_block": 4, "units_per_wave": 1, "grid_mult": 2, "walks_per_lane": 2},
+        order = ("units_per_wave", "grid_mult", "walks_per_lane", "waves_per_block",
+                 "lanes_per_walker")  # the file's key order
+        for shape in ({"waves_per_block": 1, "units_per_wave": 2, "grid_mult": 1, "walks_per_lane": 1,
+                       "lanes_per_walker": 2},
+                      {"waves_per_block": 2, "units_per_wave": 8, "grid_mult": 2, "walks_per_lane": 4,
+                       "lanes_per_walker": 1},
+                      {"waves_per_block": 4, "units_per_wave": 1, "grid_mult": 2, "walks_per_lane": 2,
+                       "lanes_per_walker": 4},
+                      {"waves_per_block": 4, "units_per_wave": 4, "grid_mult": 1, "walks_per_lane": 1,
+                       "lanes_per_walker": 64},
                       cache[key]):
             with open(path, "w") as f:
                 f.write("{\n  \"%s\": %s\n}\n" % (key, json.dumps({k: shape[k] for k in order})))
