@@ -130,11 +130,12 @@ __device__ __forceinline__ void philox4x32_10(uint32_t& c0, uint32_t& c1, uint32
 {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        // one 32x32->64-bit product per word (v_mad_u64_u32) gives both halves
+        // one 32x32->64-bit product per word (v_mad_u64_u32) gives both
+        // halves; each three-way xor is one v_bitop3_b32 (truth table 0x96)
         const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
         const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
-        const uint32_t y0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-        const uint32_t y2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        const uint32_t y0 = __builtin_amdgcn_bitop3_b32((uint32_t)(p1 >> 32), c1, k0, 0x96);
+        const uint32_t y2 = __builtin_amdgcn_bitop3_b32((uint32_t)(p0 >> 32), c3, k1, 0x96);
         c0 = y0;
         c1 = (uint32_t)p1;
         c2 = y2;
