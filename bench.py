@@ -712,8 +712,9 @@ def main():
                         "kernel_hash": khash}}
     if tune is not None:
         out["autotune"] = dict(tune, basis="wos_autotune_batch on this batch before timing: coordinate descent "
-                                            "over waves per block, units per wave, grid multiple, walks per lane; "
-                                            "ms_default = one launch with the built-in shape (4, 4, 1, 2)",
+                                            "over waves per block, units per wave, grid multiple, walks per lane, then lanes "
+                                            "per walker G doubled (then halved) while faster; ms_default = one "
+                                            "launch with the built-in shape (4, 4, 1, 2, G = 1)",
                                gain_vs_default=tune["ms_default"] / ms_step)
 
     if not args.no_plain:

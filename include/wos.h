@@ -365,8 +365,8 @@ typedef struct {
     int units_per_wave;   /* work units (query, walk range) per resident wave */
     int grid_mult;        /* grid = grid_mult x the resident blocks of the device */
     int walks_per_lane;   /* least walks each walk-carrying lane takes from a work unit */
-    int lanes_per_walker; /* 1, 2 or 4: a wave carries 64, 32 or 16 walks at once; all
-                             64 lanes share those walks' member scans */
+    int lanes_per_walker; /* G = 1, 2, 4, ..., 64: a wave carries 64 / G walks at once;
+                             all 64 lanes share those walks' member scans */
     double ms_default;    /* launch time with the built-in shape (4, 4, 1, 2, 1) */
     double ms_best;       /* launch time with the chosen shape */
     int tried;            /* shapes timed */
@@ -377,10 +377,12 @@ typedef struct {
  * (arguments as wos_estimate_batch; fused != 0: forward + backward with
  * u-bar = 1, else forward only) for launch shapes reached by coordinate
  * descent from the built-in one: waves per block {1, 2, 4}, units per wave
- * {1, 2, 4, 8, 16}, grid multiple {1, 2}, walks per lane {1, 2, 4}, lanes
- * per walker {1, 2, 4} (fewer walks per wave, more waves, when the batch has
- * too few walks to fill the device), one parameter at a time with the others held; a shape must beat the best by
- * more than 0.5 % to replace it.  The best shape is recorded for this batch
+ * {1, 2, 4, 8, 16}, grid multiple {1, 2}, walks per lane {1, 2, 4}, one
+ * parameter at a time with the others held, then lanes per walker G (fewer
+ * walks per wave, more waves, when the batch has too few walks to fill the
+ * device) doubled from the current value up to 64 while the launch gets
+ * faster, then halved likewise; a shape must beat the best by more than
+ * 0.5 % to replace it.  The best shape is recorded for this batch
  * mix (the multiset of its environments' dimension and log2 buckets of
  * obstacle, query and walk counts), in memory for the batched calls of this
  * process and, when cache_path is not NULL, in that JSON file (created or

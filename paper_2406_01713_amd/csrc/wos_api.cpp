@@ -1007,33 +1007,50 @@ int tune_batch(const wos_domain* const* envs, int n_envs, const float* queries, 
                a.walks_per_lane == b.walks_per_lane && a.waves_per_block == b.waves_per_block &&
                a.lanes_per_walker == b.lanes_per_walker;
     };
-    static const int wpbs[] = {1, 2, 4}, upws[] = {1, 2, 4, 8, 16}, gms[] = {1, 2}, wpls[] = {1, 2, 4},
-                     lpws[] = {1, 2, 4};
-    static const int* const vals_of[] = {wpbs, upws, gms, wpls, lpws};
-    static const int n_of[] = {3, 5, 2, 3, 3};
+    static const int wpbs[] = {1, 2, 4}, upws[] = {1, 2, 4, 8, 16}, gms[] = {1, 2}, wpls[] = {1, 2, 4};
+    static const int* const vals_of[] = {wpbs, upws, gms, wpls};
+    static const int n_of[] = {3, 5, 2, 3};
     auto field = [](Tune& t, int prm) -> int& {
         return prm == 0 ? t.waves_per_block : prm == 1 ? t.units_per_wave : prm == 2 ? t.grid_mult
-                                                       : prm == 3 ? t.walks_per_lane : t.lanes_per_walker;
+                                                       : t.walks_per_lane;
+    };
+    // time candidate c (or take its earlier time); adopt it past the noise guard
+    auto consider = [&](const Tune& c, bool& moved) -> bool {
+        double m = -1.0;
+        for (auto& s : seen)
+            if (same(s.first, c)) m = s.second;
+        if (m < 0.0) {
+            time_one(c, m);
+            seen.push_back({c, m});
+            ++out.tried;
+        }
+        if (e == hipSuccess && !rc && m < best_ms * (1.0 - 0.005)) {
+            cur = c;
+            best_ms = m;
+            moved = true;
+            return true;
+        }
+        return false;
     };
     for (int pass = 0; pass < 2 && e == hipSuccess && !rc; ++pass) {
         bool moved = false;
-        for (int prm = 0; prm < 5; ++prm) {
+        for (int prm = 0; prm < 4; ++prm) {
             for (int i = 0; i < n_of[prm] && e == hipSuccess && !rc; ++i) {
                 Tune c = cur;
                 field(c, prm) = vals_of[prm][i];
-                double m = -1.0;
-                for (auto& s : seen)
-                    if (same(s.first, c)) m = s.second;
-                if (m < 0.0) {
-                    time_one(c, m);
-                    seen.push_back({c, m});
-                    ++out.tried;
-                }
-                if (e == hipSuccess && !rc && m < best_ms * (1.0 - 0.005)) {
-                    cur = c;
-                    best_ms = m;
-                    moved = true;
-                }
+                consider(c, moved);
+            }
+        }
+        // lanes per walker G in 1, 2, 4, ..., 64: double (then halve) while
+        // the launch gets faster, so a batch that fills the device never
+        // pays for the large G that only a handful of walks can use
+        for (int dir = 0; dir < 2 && e == hipSuccess && !rc; ++dir) {
+            for (;;) {
+                const int g = dir == 0 ? 2 * cur.lanes_per_walker : cur.lanes_per_walker / 2;
+                if (g < 1 || g > kWave || e != hipSuccess || rc) break;
+                Tune c = cur;
+                c.lanes_per_walker = g;
+                if (!consider(c, moved)) break;
             }
         }
         if (!moved) break;
