@@ -3,7 +3,9 @@
     python -m paper_2406_01713_amd.build
 
 Every source is compiled for gfx950 only; packed-FP32 instructions are
-disabled (-packed-fp32-ops) and none are written by hand."""
+disabled (-packed-fp32-ops) and none are written by hand.  A declaration
+that shadows another (a loop-local variable hiding a parameter of the same
+name) is a build error."""
 from __future__ import annotations
 
 import os
@@ -23,7 +25,7 @@ SOURCES = ["wos_kernels.hip", "wos_api.cpp", "wos_microbench.hip"]
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-x", "hip",
          *os.environ.get("WOS_EXTRA_FLAGS", "").split(),
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-         "-Wall", "-Wno-unused-function", "-I", os.path.join(ROOT, "include")]
+         "-Wall", "-Wno-unused-function", "-Werror=shadow", "-I", os.path.join(ROOT, "include")]
 
 
 def _hipcc():
