@@ -272,7 +272,9 @@ int wos_backward(const wos_domain* dom, const void* queries, int64_t n_queries, 
  * Walk identities match wos_estimate / wos_backward called per env with
  * env_id = e, so results agree with those calls up to summation order.
  * Errors: as wos_estimate; WOS_ENOTSUP for WOS_FP64, and with grad_u for an
- * env with a point source at sigma = 0 (as wos_backward).
+ * env with a point source at sigma = 0 (as wos_backward); WOS_EINVAL for an
+ * env with more than 2^31 - 1 queries or a batch of 2^32 - 1 or more work
+ * units (each at least 64 walks).
  */
 int wos_estimate_batch(const wos_domain* const* envs, int n_envs, const float* queries,
                        const int64_t* q_offsets, const double* sigma, const double* eps,
@@ -327,6 +329,10 @@ int wos_estimate_batch_noalloc(const wos_domain* const* envs, int n_envs, const 
  *   counted); a start within eps of the boundary stops (status 1 at the goal,
  *   2 elsewhere).
  * The plan owns its scratch buffers; x must outlive the plan.
+ * Errors: WOS_EINVAL (NULL pointers, n_starts outside [1, 2^24], n_walks
+ * outside [1, 2^31], s_ub not finite and > 0, 2^32 - 1 or more work units),
+ * WOS_ENOTSUP (WOS_FP64, WOS_OUT_FP64), WOS_EHIP / WOS_ENOMEM (set-up or
+ * graph capture).
  */
 int wos_plan_create(const wos_domain* dom, float* x, int64_t n_starts, int64_t n_walks,
                     double sigma, double eps, double s_ub, uint64_t seed,

@@ -863,6 +863,9 @@ int run_batch(const wos_domain* const* envs, int n_envs, const float* queries, c
     for (int e = 0; e < n_envs; ++e) {
         if (!envs[e]) return fail(WOS_EINVAL, "envs[%d] is NULL", e);
         if (q_offsets[e + 1] < q_offsets[e]) return fail(WOS_EINVAL, "q_offsets must be non-decreasing");
+        // a query's index is a 32-bit Philox counter word and an int32 count
+        if (q_offsets[e + 1] - q_offsets[e] > INT32_MAX)
+            return fail(WOS_EINVAL, "env %d has more than 2^31 - 1 queries", e);
         if ((rc = check_device(envs[e]))) return rc;
     }
     const int64_t sumQ = q_offsets[n_envs];
@@ -909,6 +912,9 @@ int run_batch(const wos_domain* const* envs, int n_envs, const float* queries, c
     BatchLayout L;
     plan_batch(envs, q_offsets, n_envs, n_walks, kBatchStride, force, (o.flags & WOS_FULL_SCAN) != 0, src, order, hb,
                L);
+    // the kernel hands out units with a 32-bit device counter
+    if (L.total_units >= ((int64_t)1 << 32) - 1)
+        return fail(WOS_EINVAL, "the batch splits into %lld work units; at most 2^32 - 2", (long long)L.total_units);
     const size_t part_bytes = (size_t)std::max<int64_t>(L.total_units, 1) * nacc(kMaxDim) * sizeof(double);
 
     Scratch S(st);
@@ -1617,6 +1623,10 @@ int wos_plan_create(const wos_domain* D, float* x, int64_t n_starts, int64_t n_w
     BatchEnv benv1;
     int order1;
     plan_batch(envs, qoff, 1, nw, D->d, nullptr, (o.flags & WOS_FULL_SCAN) != 0, D->has_src, &order1, &benv1, L);
+    if (L.total_units >= ((int64_t)1 << 32) - 1) {
+        plan_free(P);
+        return fail(WOS_EINVAL, "the plan splits into %lld work units; at most 2^32 - 2", (long long)L.total_units);
+    }
     const int64_t S = n_starts;
     if (e == hipSuccess) e = hipMalloc(&P->u, S * sizeof(float));
     if (e == hipSuccess) e = hipMalloc(&P->grad, S * kBatchStride * sizeof(float));

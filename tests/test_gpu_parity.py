@@ -817,6 +817,25 @@ def test_edge_cases(B, oracle):
                        torch.empty(4, device="cuda"))
 
 
+def test_batch_rejects_counts_beyond_its_indices(B):
+    """Query and work-unit counts past what the kernels index (32-bit query
+    counters, a 32-bit unit counter) come back as errors before any device
+    work: an env with 2^31 queries, and three envs of 2^31 - 1 queries (about
+    6.4e9 work units)."""
+    import torch
+    s = subset("c3", 4, 64, seed=1)
+    dom = B.Domain(s)
+    q = torch.zeros(4, 8, device="cuda")
+    u = torch.empty(4, device="cuda")
+    with pytest.raises(B.WosError, match="queries"):
+        B.wos_estimate_batch([dom], q, [0, 2 ** 31], [2.0], [1e-4], 64, 0, u)
+    n = 2 ** 31 - 1
+    with pytest.raises(B.WosError, match="work units"):
+        B.wos_estimate_batch([dom] * 3, q, [0, n, 2 * n, 3 * n], [2.0] * 3, [1e-4] * 3, 64, 0, u)
+    B.wos_estimate_batch([dom], q, [0, 4], [2.0], [1e-4], 64, 0, u)  # the library still works
+    torch.cuda.synchronize()
+
+
 # -------------------------------------------- full-size sampled parity ----
 
 @pytest.mark.parametrize("fused", [False, True])
