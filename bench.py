@@ -396,12 +396,35 @@ def near_goal_starts(s, n, seed=5):
     return S.near_goal_points(s, n, gap_lo=0.05, gap_hi=0.5, seed=seed, delta=0.02)
 
 
-def planning(B, torch, n_steps, near_goal=False, source=False):
+TUNE_CACHE = None  # --tune-cache: where the searches also record their shapes
+
+
+def tune_plan(B, torch, dom, s, starts, n_walks, sigma=None):
+    """The launch-shape search on a plan's own batch (its starts as the
+    queries of one environment) before the plan is built: the shape is
+    recorded under the batch's mix key, which the plan's captured launch
+    looks up."""
+    q = torch.zeros(len(starts), 8, dtype=torch.float32, device="cuda")
+    q[:, :s["d"]] = torch.as_tensor(np.asarray(starts), dtype=torch.float32)
+    sig = s["sigma"] if sigma is None else sigma
+    # the fused launch of a batch needs d u / d sigma, which a point source
+    # has only for sigma > 0: there the forward launch stands in
+    fused = not (s.get("source") is not None and sig == 0.0)
+    t = time.perf_counter()
+    r = B.wos_autotune_batch([dom], q, [0, len(starts)], [sig], [s["eps"]], n_walks, s["seed"], fused=fused,
+                             cache_path=TUNE_CACHE)
+    r["fused"] = fused
+    r["search_s"] = time.perf_counter() - t
+    return r
+
+
+def planning(B, torch, n_steps, near_goal=False, source=False, tune=True):
     from paper_2406_01713_amd import scenes as S
     s0 = S.scene_c5()
     starts = near_goal_starts(s0, len(s0["queries"])) if near_goal else s0["queries"]
     s = S.with_source(s0, s0["goal_c"]) if source else s0
     dom = B.Domain(s)
+    shape = tune_plan(B, torch, dom, s, starts, s["n_walks"]) if tune else None
     x = torch.as_tensor(starts, dtype=torch.float32, device="cuda")
     plan = B.Plan(dom, x, s["n_walks"], s["sigma"], s["eps"], s["s_ub"], s["seed"])
     plan.step(1)
@@ -416,6 +439,8 @@ def planning(B, torch, n_steps, near_goal=False, source=False):
            "walks_per_gradient": s["n_walks"], "obstacles": "512 spheres + 512 boxes",
            "arrived": int((status == 1).sum()), "stopped_elsewhere": int((status == 2).sum()),
            "stalls_total": int(stalls.sum()), "mean_path_len": float(pl.mean())}
+    if shape is not None:
+        res["autotune"] = shape
     del plan
     return res
 
@@ -483,7 +508,7 @@ def eval_env_sweep(B, torch, dims=(2, 3, 4, 5), ns=(10 ** 3, 10 ** 4, 10 ** 5, 1
     return out
 
 
-def rr_validation(B, torch, n_walks=100000, max_steps=300):
+def rr_validation(B, torch, n_walks=100000, max_steps=300, tune=True):
     """The RR task of Sec. VII (Table II): gradient ascent from q_start to a
     unit impulse at q_goal, 1e5 walks per gradient, s = min(0.1, d/2),
     eps = 0.02, c = 0 and 5, with the IK-point distance (N_col = 200) and the
@@ -498,8 +523,10 @@ def rr_validation(B, torch, n_walks=100000, max_steps=300):
     for distance in ("ik", "lipschitz"):
         for sigma in (0.0, 5.0):
             s = S.scene_rr(distance, sigma=sigma, n_walks=n_walks)
+            dom = B.Domain(s)
+            shape = tune_plan(B, torch, dom, s, [S.RR_Q_START], n_walks) if tune else None
             x = torch.as_tensor(np.array([S.RR_Q_START]), dtype=torch.float32, device="cuda")
-            plan = B.Plan(B.Domain(s), x, n_walks, s["sigma"], s["eps"], s["s_ub"], s["seed"])
+            plan = B.Plan(dom, x, n_walks, s["sigma"], s["eps"], s["s_ub"], s["seed"])
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
             e0.record(st)
@@ -519,13 +546,15 @@ def rr_validation(B, torch, n_walks=100000, max_steps=300):
                 "path_length": float(path[0]), "arrived": int(sts[0]) == 1, "plan_steps": int(step[0]),
                 "stalls": int(stalls[0]), "ms_per_plan_step": e0.elapsed_time(e1) / max(int(step[0]), 1),
                 "end": [float(v) for v in x.cpu().numpy()[0]]}
+            if shape is not None:
+                out["runs"][f"{distance}_c{sigma:g}"]["autotune"] = shape
             del plan
             log(f"RR {distance} c={sigma:g}: path {float(path[0]):.3f}, arrived {int(sts[0]) == 1}, "
                 f"{int(step[0])} steps")
     return out
 
 
-def eval_env_paths(B, torch, sigmas=(0.1, 1.0, 10.0), n_walks=100000, max_steps=600):
+def eval_env_paths(B, torch, sigmas=(0.1, 1.0, 10.0), n_walks=100000, max_steps=600, tune=True):
     """Screening and path length in the evaluation environment (Sec. VI-A,
     d = 2, k_r = 0.3, eps = 0.01): gradient ascent from x_start,1 = (-8, 0)
     to the unit impulse at (8, 0) with 1e5 walks per gradient and
@@ -538,8 +567,10 @@ def eval_env_paths(B, torch, sigmas=(0.1, 1.0, 10.0), n_walks=100000, max_steps=
     out = {"start": [-8.0, 0.0], "goal": [8.0, 0.0], "n_walks": n_walks, "s_ub": 0.1, "runs": {}}
     for c in sigmas:
         s = S.scene_eval_env(2, k_r=0.3, sigma=c, eps=1e-2)
+        dom = B.Domain(s)
+        shape = tune_plan(B, torch, dom, s, s["queries"][:1], n_walks, sigma=c) if tune else None
         x = torch.as_tensor(s["queries"][:1], dtype=torch.float32, device="cuda")
-        plan = B.Plan(B.Domain(s), x, n_walks, c, s["eps"], 0.1, s["seed"])
+        plan = B.Plan(dom, x, n_walks, c, s["eps"], 0.1, s["seed"])
         steps = 0
         while steps < max_steps:
             plan.step(20)
@@ -550,6 +581,8 @@ def eval_env_paths(B, torch, sigmas=(0.1, 1.0, 10.0), n_walks=100000, max_steps=
         out["runs"][f"c={c:g}"] = {"path_length": float(path[0]), "arrived": int(sts[0]) == 1,
                                    "plan_steps": int(step[0]), "stalls": int(stalls[0]),
                                    "end": [float(v) for v in x.cpu().numpy()[0]]}
+        if shape is not None:
+            out["runs"][f"c={c:g}"]["autotune"] = shape
         del plan
         log(f"eval env path c={c:g}: length {float(path[0]):.2f}, arrived {int(sts[0]) == 1}, "
             f"stalls {int(stalls[0])}")
@@ -580,6 +613,8 @@ def main():
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first copy this many MiB device-to-device 3 times (counter calibration)")
     args = ap.parse_args()
+    global TUNE_CACHE
+    TUNE_CACHE = args.tune_cache
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one MI355X: the walk kernels run on a single GPU "
               "(walk ranges and queries would shard across GPUs with one all-reduce of partial sums; not run here). "
@@ -817,24 +852,25 @@ def main():
 
     if not args.no_plan:
         t = time.perf_counter()
-        out["planning_d7"] = planning(B, torch, args.plan_steps)
-        out["planning_d7_near_goal"] = planning(B, torch, args.plan_steps, near_goal=True)
+        tune_p = not (args.no_tune or args.load_tune)
+        out["planning_d7"] = planning(B, torch, args.plan_steps, tune=tune_p)
+        out["planning_d7_near_goal"] = planning(B, torch, args.plan_steps, near_goal=True, tune=tune_p)
         log(f"planning: {out['planning_d7']['ms_per_step']:.1f} ms/step; near goal "
             f"{out['planning_d7_near_goal']['ms_per_step']:.1f} ms/step, "
             f"{out['planning_d7_near_goal']['arrived']} arrived ({time.perf_counter() - t:.1f} s)")
         if not args.no_source:
             t = time.perf_counter()
-            out["planning_d7_point_source"] = planning(B, torch, args.plan_steps, source=True)
+            out["planning_d7_point_source"] = planning(B, torch, args.plan_steps, source=True, tune=tune_p)
             out["planning_d7_point_source_near_goal"] = planning(B, torch, args.plan_steps, near_goal=True,
-                                                                 source=True)
+                                                                 source=True, tune=tune_p)
             log(f"planning to a point source: {out['planning_d7_point_source']['arrived']} / "
                 f"{out['planning_d7_point_source_near_goal']['arrived']} arrived "
                 f"({time.perf_counter() - t:.1f} s)")
 
     if not args.no_plan:
         t = time.perf_counter()
-        out["rr_validation"] = rr_validation(B, torch)
-        out["eval_env_paths"] = eval_env_paths(B, torch)
+        out["rr_validation"] = rr_validation(B, torch, tune=not (args.no_tune or args.load_tune))
+        out["eval_env_paths"] = eval_env_paths(B, torch, tune=not (args.no_tune or args.load_tune))
         log(f"RR validation and evaluation-environment paths ({time.perf_counter() - t:.1f} s)")
 
     if not args.no_eval_env:
