@@ -446,11 +446,12 @@ int wos_debug_walks(const wos_domain* dom, const double* query, uint32_t q_index
 
 /*
  * wos_debug_clusters -- host only, no device: the obstacle clusters that
- * wos_create_domain builds for this obstacle set (empty below 64 obstacles).
+ * wos_create_domain builds for this obstacle set (empty below 64 obstacles),
+ * WOS_CLUSTER_ROWS obstacle rows per cluster.
  *   spheres, boxes   as wos_create_domain (either may be NULL)
  *   fp64             0: the FP32 tables, 1: the FP64 tables
  *   out_n_cl         host int64[2]: sphere clusters, box clusters
- *   order_sph        host int64, capacity n_cl_sph * 8 (may be NULL): caller
+ *   order_sph        host int64, capacity n_cl_sph * WOS_CLUSTER_ROWS (may be NULL): caller
  *                    index of each clustered sphere row, -1 for padding
  *   bnd_sph          host double, capacity n_cl_sph * (d + 1) (may be NULL):
  *                    bounding sphere (centre, enlarged radius) per cluster,
@@ -459,6 +460,7 @@ int wos_debug_walks(const wos_domain* dom, const double* query, uint32_t q_index
  * Capacities are taken from the counts this call computes: call once with
  * NULL arrays to learn them.  Errors: WOS_EDIM, WOS_EINVAL.
  */
+#define WOS_CLUSTER_ROWS 8
 int wos_debug_clusters(int d, const wos_spheres* spheres, const wos_boxes* boxes, int fp64,
                        int64_t* out_n_cl, int64_t* order_sph, double* bnd_sph, int64_t* order_box,
                        double* bnd_box);

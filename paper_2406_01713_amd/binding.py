@@ -22,7 +22,8 @@ WOS_FP32, WOS_FP64, WOS_FULL_SCAN, WOS_SCALAR_CULL, WOS_WAVE_SCAN = 0, 1, 2, 4, 
 WOS_OUT_FP64 = 16
 WOS_NOALLOC_SCRATCH_BYTES = 64 << 20
 WOS_NOALLOC_MAX_ENVS = 1024
-CLUSTER = 8
+WOS_CLUSTER_ROWS = 8  # obstacle rows per cluster (wos_debug_clusters capacities)
+CLUSTER = WOS_CLUSTER_ROWS
 BATCH_STATS = 15
 WOS_OUTER_BOX, WOS_OUTER_BALL = 0, 1
 BATCH_STRIDE = 8

@@ -1319,6 +1319,8 @@ int wos_varadhan(const void* u, const void* grad_u, int64_t n, int d, int stride
     return WOS_OK;
 }
 
+static_assert(kCluster == WOS_CLUSTER_ROWS, "the header states the cluster size callers size their arrays by");
+
 int wos_debug_clusters(int d, const wos_spheres* spheres, const wos_boxes* boxes, int fp64, int64_t* out_n_cl,
                        int64_t* order_sph, double* bnd_sph, int64_t* order_box, double* bnd_box)
 {

@@ -26,6 +26,7 @@ def _sets():
 
 @pytest.mark.parametrize("fp64", [False, True])
 def test_cluster_order_is_a_padded_permutation(B, fp64):
+    assert CL == B.WOS_CLUSTER_ROWS
     for name, s in _sets():
         out = B.wos_debug_clusters(s["d"], s["sph_c"], s["sph_r"], s["box_c"], s["box_h"], fp64=fp64)
         for kind, n in (("sph", len(s["sph_r"])), ("box", len(s["box_c"]))):
