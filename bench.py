@@ -81,7 +81,9 @@ def executed_flops(s, st):
     """Distance arithmetic that one env's walks actually executed, from the
     work columns of the batched stats (per-walk means of sphere and box
     member distances), split by the unit that runs it:
-      valu  member spheres 3d + 2, member boxes 5d + 1, the goal 3d + 2 and
+      valu  member spheres 3d + 2, member boxes 5d + 1, cluster bounding
+            boxes 6d + 2 (per axis two differences, a three-way max, a
+            multiply-add; a square root and the margin), the goal 3d + 2 and
             the outer box 4d per walk-step: the vector ALUs;
       mfma  the cluster test, 16 clusters per matrix-core tile, 12-term dot
             product per (walker, cluster) pair, for every cluster tile at
@@ -90,7 +92,8 @@ def executed_flops(s, st):
     d, n = s["d"], s["n_walks"]
     steps = st[:, 9]
     goal = 1.0 if s.get("goal_r") is not None else 0.0
-    valu = (st[:, 12] * (3 * d + 2) + st[:, 13] * (5 * d + 1) + steps * (goal * (3 * d + 2) + 4 * d)) * n
+    valu = (st[:, 12] * (3 * d + 2) + st[:, 13] * (5 * d + 1) + st[:, 15] * (6 * d + 2)
+            + steps * (goal * (3 * d + 2) + 4 * d)) * n
     tiles = -(-n_clusters(len(s["sph_r"])) // 16) + -(-n_clusters(len(s["box_h"])) // 16)
     mfma = steps * n * tiles * 16 * MFMA_FLOP_PER_PAIR
     return float(valu.sum()), float(mfma.sum()), float((steps * n).sum())
@@ -216,7 +219,7 @@ class Batch:
         self.eps = [e["eps"] for e in envs]
         self.u = torch.empty(n, device=dev)
         self.g = torch.empty(n, 8, device=dev)
-        self.st = torch.empty(n, 15, dtype=torch.float64, device=dev)
+        self.st = torch.empty(n, B.BATCH_STATS, dtype=torch.float64, device=dev)
         self.ubar = torch.ones(n, device=dev)
         self.dx = torch.empty(n, 8, device=dev)
         self.ds = torch.empty(len(envs), dtype=torch.float64, device=dev)
@@ -719,9 +722,10 @@ def main():
                         "unit": "TFLOP/s", "frac": valu_rate / PEAK_FP32_TFLOPS,
                         "traffic": counters.get("bytes_per_launch"),
                         "basis": "distance arithmetic executed on the vector ALUs: member sphere (3d + 2) and "
-                                 "box (5d + 1) distances, the goal (3d + 2) and the outer box (4d) per walk-step, "
-                                 "counted by the kernel's work tallies; the cluster test runs on the matrix "
-                                 "cores and is reported under 'mfma'",
+                                 "box (5d + 1) distances, cluster bounding-box tests (6d + 2) of the pairs the "
+                                 "matrix-core test keeps, the goal (3d + 2) and the outer box (4d) per "
+                                 "walk-step, counted by the kernel's work tallies; the cluster test runs on the "
+                                 "matrix cores and is reported under 'mfma'",
                         "mfma": {"achieved": mfma_rate, "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
                                  "frac": mfma_rate / PEAK_FP32_MFMA_TFLOPS, "flops_per_launch": mfma,
                                  "basis": "cluster tests (12-term dot product, 24 FLOP per walker and cluster) "

@@ -61,6 +61,7 @@ extern "C" {
 #define WOS_MIN_DIM 2
 #define WOS_MAX_DIM 8
 #define WOS_BATCH_STRIDE 8 /* row stride of batched query / gradient arrays */
+#define WOS_BATCH_STATS 16 /* columns of a batched stats row */
 
 /* flags */
 #define WOS_FP32 0u
@@ -258,13 +259,15 @@ int wos_backward(const wos_domain* dom, const void* queries, int64_t n_queries, 
  *   seed       Philox key; env e uses env_id = e
  *   out_u      device float, sum Q
  *   out_grad   device float, (sum Q) x 8, or NULL
- *   out_stats  device double, (sum Q) x 15, or NULL: columns 0..11 as
- *              wos_estimate with d = 8 columns reserved for se_grad, then
+ *   out_stats  device double, (sum Q) x WOS_BATCH_STATS, or NULL: columns
+ *              0..11 as wos_estimate with d = 8 columns reserved for
+ *              se_grad, then
  *              [12] sphere distances evaluated per walk (mean),
  *              [13] box distances evaluated per walk (mean),
- *              [14] cluster bounds evaluated per walk (mean); these count
- *              the work the obstacle scan did after culling (per walk they
- *              wrap modulo 2^32)
+ *              [14] cluster bounds evaluated per walk (mean),
+ *              [15] cluster bounding boxes tested per walk (mean); these
+ *              count the work the obstacle scan did after culling (per walk
+ *              they wrap modulo 2^32)
  *   grad_u     device float, sum Q, or NULL for forward only
  *   out_dx     device float, (sum Q) x 8 (required with grad_u)
  *   out_dsigma device double, n_envs (required with grad_u)
@@ -294,10 +297,10 @@ int wos_estimate_batch(const wos_domain* const* envs, int n_envs, const float* q
  * about (sizeof env table) x n_envs bytes from static host staging and clears
  * the counter with a fill kernel.
  * Limits: at most WOS_NOALLOC_MAX_ENVS environments, and 256-byte-aligned
- * [counter | tables | 200 bytes per work unit] within the array; a work unit
- * is one (query, walk range), so a batch needs about 200 bytes per query
+ * [counter | tables | 208 bytes per work unit] within the array; a work unit
+ * is one (query, walk range), so a batch needs about 208 bytes per query
  * when its queries take a few thousand walks (the full 512-env ragged batch,
- * 266081 queries x 2048 walks, needs 54 MB).  A batch beyond either limit
+ * 266081 queries x 2048 walks, needs 56 MB).  A batch beyond either limit
  * returns WOS_EINVAL before anything is launched.
  * Concurrency: every call on a device uses that device's one array, which
  * keeps the last call's contents.  Host threads are serialised by the
@@ -464,6 +467,23 @@ int wos_debug_walks(const wos_domain* dom, const double* query, uint32_t q_index
 int wos_debug_clusters(int d, const wos_spheres* spheres, const wos_boxes* boxes, int fp64,
                        int64_t* out_n_cl, int64_t* order_sph, double* bnd_sph, int64_t* order_box,
                        double* bnd_box);
+
+/*
+ * wos_debug_cluster_boxes -- host only, no device: the bounding boxes that
+ * the FP32 kernels test the (walker, cluster) pairs kept by the cluster
+ * bound against, one per cluster of wos_debug_clusters (same cluster order).
+ *   spheres, boxes   as wos_create_domain (either may be NULL)
+ *   out_n_cl         host int64[2]: sphere clusters, box clusters
+ *   box_sph          host double, capacity n_cl_sph * 2 d (may be NULL): per
+ *                    cluster lo[d] then hi[d], the FP32 values of the device
+ *                    table (the members' box enlarged by 2^-16 of its
+ *                    diagonal on every side, rounded outwards)
+ *   box_box          the same for box obstacles
+ * Capacities are taken from the counts this call computes: call once with
+ * NULL arrays to learn them.  Errors: WOS_EDIM, WOS_EINVAL.
+ */
+int wos_debug_cluster_boxes(int d, const wos_spheres* spheres, const wos_boxes* boxes, int64_t* out_n_cl,
+                            double* box_sph, double* box_box);
 
 /*
  * wos_microbench -- issue-rate microbenchmark on the current device, used as

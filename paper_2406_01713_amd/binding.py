@@ -24,16 +24,19 @@ WOS_NOALLOC_SCRATCH_BYTES = 64 << 20
 WOS_NOALLOC_MAX_ENVS = 1024
 WOS_CLUSTER_ROWS = 8  # obstacle rows per cluster (wos_debug_clusters capacities)
 CLUSTER = WOS_CLUSTER_ROWS
-BATCH_STATS = 15
+WOS_BATCH_STATS = 16  # columns of a batched stats row
+BATCH_STATS = WOS_BATCH_STATS
 WOS_OUTER_BOX, WOS_OUTER_BALL = 0, 1
-BATCH_STRIDE = 8
+WOS_BATCH_STRIDE = 8
+BATCH_STRIDE = WOS_BATCH_STRIDE
 MAX_DIM = 8
 
 EXPORTED = ["wos_create_domain", "wos_destroy_domain", "wos_domain_dim", "wos_estimate",
             "wos_backward", "wos_estimate_batch", "wos_estimate_batch_noalloc", "wos_plan_create", "wos_plan_step",
             "wos_plan_buffers", "wos_plan_read", "wos_plan_destroy", "wos_autotune", "wos_autotune_batch",
             "wos_set_autotune_cache",
-            "wos_debug_walks", "wos_debug_clusters", "wos_varadhan", "wos_microbench", "wos_last_error"]
+            "wos_debug_walks", "wos_debug_clusters", "wos_debug_cluster_boxes", "wos_varadhan", "wos_microbench",
+            "wos_last_error"]
 
 
 class WosError(RuntimeError):
@@ -119,6 +122,7 @@ def _load():
                                   C.POINTER(Options), dp]
     L.wos_debug_clusters.argtypes = [C.c_int, C.POINTER(Spheres), C.POINTER(Boxes), C.c_int,
                                      C.POINTER(i64), C.POINTER(i64), dp, C.POINTER(i64), dp]
+    L.wos_debug_cluster_boxes.argtypes = [C.c_int, C.POINTER(Spheres), C.POINTER(Boxes), C.POINTER(i64), dp, dp]
     L.wos_microbench.argtypes = [C.c_int, dp, dp]
     L.wos_varadhan.argtypes = [vp, vp, i64, C.c_int, C.c_int, C.c_double, vp, vp, C.POINTER(Options), vp]
     L.wos_last_error.restype = C.c_char_p
@@ -276,6 +280,29 @@ def wos_debug_walks(dom, query, q_index, w0, n, sigma, eps, seed, opt=None):
                               float(eps), int(seed), C.byref(opt) if opt is not None else None,
                               _dp(out)))
     return out
+
+
+def wos_debug_cluster_boxes(d, sph_c=None, sph_r=None, box_c=None, box_h=None):
+    """Host-only cluster bounding boxes of an obstacle set: dict with, per
+    kind ('sph', 'box'), an n_cl x 2d array of lo then hi per cluster (the
+    FP32 values of the device table), clusters in wos_debug_clusters order."""
+    keep = []
+    sp = bx = None
+    if sph_c is not None and len(sph_r):
+        c, r = _f64(sph_c), _f64(sph_r)
+        keep += [c, r]
+        sp = Spheres(len(r), _dp(c), _dp(r))
+    if box_c is not None and len(box_c):
+        c, h = _f64(box_c), _f64(box_h)
+        keep += [c, h]
+        bx = Boxes(len(c), _dp(c), _dp(h))
+    n_cl = (C.c_int64 * 2)()
+    args = (int(d), C.byref(sp) if sp else None, C.byref(bx) if bx else None)
+    check(lib.wos_debug_cluster_boxes(*args, n_cl, None, None))
+    b_s = np.zeros((n_cl[0], 2 * d))
+    b_b = np.zeros((n_cl[1], 2 * d))
+    check(lib.wos_debug_cluster_boxes(*args, n_cl, _dp(b_s), _dp(b_b)))
+    return {"sph": b_s, "box": b_b}
 
 
 def wos_debug_clusters(d, sph_c=None, sph_r=None, box_c=None, box_h=None, fp64=False):

@@ -97,6 +97,7 @@ struct wos_domain {
     double* cl_d = nullptr;
     size_t off_sph_bnd = 0, off_box_cl = 0, off_box_bnd = 0;
     size_t off_sph_mf = 0, off_box_mf = 0;  // matrix-core features (FP32 buffer only)
+    size_t off_sph_cb = 0, off_box_cb = 0;  // cluster bounding boxes (FP32 buffer only)
 };
 
 namespace {
@@ -175,6 +176,8 @@ int make_env(const wos_domain* D, double sigma, double eps, uint64_t seed, uint3
     p.box_bnd = cl ? cl + D->off_box_bnd : nullptr;
     p.sph_mf = D->cl_f ? D->cl_f + D->off_sph_mf : nullptr;
     p.box_mf = D->cl_f ? D->cl_f + D->off_box_mf : nullptr;
+    p.sph_cb = D->cl_f ? D->cl_f + D->off_sph_cb : nullptr;
+    p.box_cb = D->cl_f ? D->cl_f + D->off_box_cb : nullptr;
     p.use_mfma = (sizeof(T) != 4 || (o.flags & WOS_SCALAR_CULL)) ? 0 : (o.flags & WOS_WAVE_SCAN) ? 1 : 2;
     // a pair-queue entry holds the cluster index in 26 bits
     if (p.use_mfma == 2 && (D->n_cl_sph >= (1 << 26) || D->n_cl_box >= (1 << 26))) p.use_mfma = 1;
@@ -380,6 +383,48 @@ void build_clusters(int d, int64_t n, bool box, const std::vector<int64_t>& idx,
         T r = (T)want;
         if ((double)r < want) r = std::nextafter(r, std::numeric_limits<T>::infinity());
         b[d] = r;
+    }
+}
+
+// Bounding boxes of the clusters (FP32 kernels, see kClusterBox) from the
+// caller-order FP32 rows, in cluster order: per cluster lo[kMaxDim] then
+// hi[kMaxDim], the box of its members (centres -+ radius, or -+ half-widths)
+// enlarged by delta = 2^-16 times its diagonal (plus a tiny absolute term) on
+// every side, computed in FP64 and rounded outwards to FP32.  The margin
+// covers the rounding of the kernel's box and member distances (see
+// box_round); padding rows of the last cluster are not members.
+void build_cluster_boxes(int d, int64_t n, bool box, const std::vector<int64_t>& idx, const float* rows, int S,
+                         float* out)
+{
+    const int64_t n_cl = (n + kCluster - 1) / kCluster;
+    for (int64_t g = 0; g < n_cl; ++g) {
+        const int64_t j0 = g * kCluster, j1 = std::min<int64_t>(n, j0 + kCluster);
+        double lo[kMaxDim], hi[kMaxDim];
+        for (int i = 0; i < d; ++i) {
+            lo[i] = INFINITY;
+            hi[i] = -INFINITY;
+        }
+        for (int64_t k = j0; k < j1; ++k) {
+            const float* row = rows + idx[k] * S;
+            for (int i = 0; i < d; ++i) {
+                const double ext = box ? (double)row[d + i] : (double)row[d];
+                lo[i] = std::min(lo[i], (double)row[i] - ext);
+                hi[i] = std::max(hi[i], (double)row[i] + ext);
+            }
+        }
+        double diag = 0.0;
+        for (int i = 0; i < d; ++i) diag += (hi[i] - lo[i]) * (hi[i] - lo[i]);
+        const double delta = std::sqrt(diag) * 0x1p-16 + 0x1p-100;
+        float* o = out + g * kClusterBox;
+        for (int i = 0; i < kClusterBox; ++i) o[i] = 0.0f;
+        for (int i = 0; i < d; ++i) {
+            const double l = lo[i] - delta, h = hi[i] + delta;
+            float lf = (float)l, hf = (float)h;
+            if ((double)lf > l) lf = std::nextafter(lf, -std::numeric_limits<float>::infinity());
+            if ((double)hf < h) hf = std::nextafter(hf, std::numeric_limits<float>::infinity());
+            o[i] = lf;
+            o[kMaxDim + i] = hf;
+        }
     }
 }
 
@@ -1247,7 +1292,10 @@ int wos_create_domain(int d, const wos_spheres* spheres, const wos_boxes* boxes,
     const size_t mf_b = D->n_cl_box ? (size_t)((D->n_cl_box + kMfmaTile - 1) / kMfmaTile + 1) * 64 * 4 : 0;
     D->off_sph_mf = (cl_elems + 3) / 4 * 4;  // 16-byte aligned float4 rows
     D->off_box_mf = D->off_sph_mf + mf_s;
-    const size_t cf_elems = D->off_box_mf + mf_b;
+    // cluster bounding boxes, also FP32 only (16-byte aligned rows)
+    D->off_sph_cb = D->off_box_mf + mf_b;
+    D->off_box_cb = D->off_sph_cb + (size_t)D->n_cl_sph * kClusterBox;
+    const size_t cf_elems = D->off_box_cb + (size_t)D->n_cl_box * kClusterBox;
     if (e == hipSuccess && cl_elems > 0) {
         std::vector<float> cf(cf_elems, 0.f);
         std::vector<double> cd(cl_elems, 0.0);
@@ -1265,6 +1313,8 @@ int wos_create_domain(int d, const wos_spheres* spheres, const wos_boxes* boxes,
             build_mfma_features(d, D->n_cl_sph, cf.data() + D->off_sph_bnd, cf.data() + D->off_sph_mf);
         if (D->n_cl_box)
             build_mfma_features(d, D->n_cl_box, cf.data() + D->off_box_bnd, cf.data() + D->off_box_mf);
+        if (D->n_cl_sph) build_cluster_boxes(d, ns, false, idx_s, sf.data(), ss, cf.data() + D->off_sph_cb);
+        if (D->n_cl_box) build_cluster_boxes(d, nb, true, idx_b, bf.data(), bs, cf.data() + D->off_box_cb);
         e = hipMalloc(&D->cl_f, cf_elems * sizeof(float));
         if (e == hipSuccess) e = hipMalloc(&D->cl_d, cl_elems * sizeof(double));
         if (e == hipSuccess) e = hipMemcpy(D->cl_f, cf.data(), cf_elems * sizeof(float), hipMemcpyHostToDevice);
@@ -1320,6 +1370,8 @@ int wos_varadhan(const void* u, const void* grad_u, int64_t n, int d, int stride
 }
 
 static_assert(kCluster == WOS_CLUSTER_ROWS, "the header states the cluster size callers size their arrays by");
+static_assert(kBatchStats == WOS_BATCH_STATS && kBatchStride == WOS_BATCH_STRIDE,
+              "the header states the batched row widths callers size their arrays by");
 
 int wos_debug_clusters(int d, const wos_spheres* spheres, const wos_boxes* boxes, int fp64, int64_t* out_n_cl,
                        int64_t* order_sph, double* bnd_sph, int64_t* order_box, double* bnd_box)
@@ -1358,6 +1410,38 @@ int wos_debug_clusters(int d, const wos_spheres* spheres, const wos_boxes* boxes
         }
         for (int64_t g = 0; g < n_cl[k]; ++g)
             for (int i = 0; i <= d; ++i) bnd[k][g * (d + 1) + i] = b[g * SB + i];
+    }
+    return WOS_OK;
+}
+
+int wos_debug_cluster_boxes(int d, const wos_spheres* spheres, const wos_boxes* boxes, int64_t* out_n_cl,
+                            double* box_sph, double* box_box)
+{
+    if (d < WOS_MIN_DIM || d > WOS_MAX_DIM) return fail(WOS_EDIM, "d = %d outside [%d, %d]", d, WOS_MIN_DIM, WOS_MAX_DIM);
+    if (!out_n_cl) return fail(WOS_EINVAL, "out_n_cl is NULL");
+    int rc = check_obstacles(d, spheres, boxes);
+    if (rc) return rc;
+    const int64_t ns = spheres ? spheres->n : 0, nb = boxes ? boxes->n : 0;
+    std::vector<float> sf, bf;
+    std::vector<double> sd, bd;
+    obstacle_rows(d, spheres, boxes, sf, sd, bf, bd);
+    std::vector<int64_t> idx[2];
+    const int64_t n_cl[2] = {cluster_order(d, ns, ns ? spheres->centers : nullptr, idx[0]),
+                             cluster_order(d, nb, nb ? boxes->centers : nullptr, idx[1])};
+    out_n_cl[0] = n_cl[0];
+    out_n_cl[1] = n_cl[1];
+    const int64_t n[2] = {ns, nb};
+    const int S[2] = {sph_stride(d), box_stride(d)};
+    double* out[2] = {box_sph, box_box};
+    for (int k = 0; k < 2; ++k) {
+        if (!n_cl[k] || !out[k]) continue;
+        std::vector<float> cb((size_t)n_cl[k] * kClusterBox);
+        build_cluster_boxes(d, n[k], k == 1, idx[k], k ? bf.data() : sf.data(), S[k], cb.data());
+        for (int64_t g = 0; g < n_cl[k]; ++g)
+            for (int i = 0; i < d; ++i) {
+                out[k][g * 2 * d + i] = cb[g * kClusterBox + i];
+                out[k][g * 2 * d + d + i] = cb[g * kClusterBox + kMaxDim + i];
+            }
     }
     return WOS_OK;
 }

@@ -484,13 +484,23 @@ __device__ __forceinline__ float float_of_ord(uint32_t o)
 // tally is one wave-level count for the work statistics.  Callers run the
 // step on every lane of the wave (idle lanes with live false), so the tally
 // is updated in wave-uniform control flow.  pairs: the wave's LDS slice of
-// kPairLds words for the pair-compacted scan (kPairCap queue entries of
-// cluster << 6 | walker, then the 64 walkers' minima), owned by the kernel.
+// kPairLds words for the pair-compacted scan (kPairCap entries of the first
+// queue, kBoxQueue of the member queue, both cluster << 6 | walker, then the
+// 64 walkers' minima), owned by the kernel.  cbox: cluster bounding boxes
+// tested (pair-compacted scan only).
 struct WorkCount {
-    uint64_t sph = 0, box = 0;
+    uint64_t sph = 0, box = 0, cbox = 0;
     uint32_t* pairs;
     __device__ explicit WorkCount(uint32_t* p) : pairs(p) {}
 };
+
+// Walker lane of a queue entry: its walker field q = 16 rt + 4 r + g (see
+// cluster_min_pairs) names lane 16 rt + 4 g + r.
+__device__ __forceinline__ int entry_walker(uint32_t e)
+{
+    const uint32_t q = e & (kWave - 1);
+    return (int)((q & 0x30u) | ((q & 3u) << 2) | ((q >> 2) & 3u));
+}
 
 // Evaluate queue entries [base, base + count), count <= 64, one per lane.
 // All lanes of the wave take part (the walker positions move by lane
@@ -503,10 +513,7 @@ __device__ __forceinline__ void pair_round(cptr<float> rows, int n_cl, const uin
     const int lane = threadIdx.x & (kWave - 1);
     const bool act = lane < count;
     const uint32_t e = act ? queue[base + lane] : 0u;
-    // walker field q = 16 rt + 4 r + g (see cluster_min_pairs) -> the walker's
-    // lane 16 rt + 4 g + r
-    const uint32_t q = e & (kWave - 1);
-    const int w = (int)((q & 0x30u) | ((q & 3u) << 2) | ((q >> 2) & 3u));
+    const int w = entry_walker(e);
     int c = (int)(e >> 6);
     c = c < n_cl ? c : n_cl - 1;  // an entry never points past the table
     float xw[D];
@@ -522,6 +529,62 @@ __device__ __forceinline__ void pair_round(cptr<float> rows, int n_cl, const uin
             m = Math<float>::min(m, BOX ? box_dist<float, D>(xw, r + j * S) : sphere_dist<float, D>(xw, r + j * S));
         atomicMin(&best[w], ord_of(m));
     }
+}
+
+// Bounding-box test of queue entries [base, base + count), count <= 64, one
+// per lane: an entry passes unless the distance from its walker to its
+// cluster's box, times Cull<float>::shrink, exceeds max(thr, 0) of that
+// walker; passing entries are appended to the member queue mq (mqn entries,
+// fewer than 64 on entry, wave-uniform).
+//
+// Soundness (FP32, unit roundoff u = 2^-24): the stored box contains the
+// members' box enlarged by delta = 2^-16 times its diagonal in every
+// direction, so a walker at distance L from the members' box is at most
+// max(0, L - delta) from the stored one.  The computed box distance is
+// within (D / 2 + 4) u of that relatively, the shrink takes 2^-16 off, and a
+// member's computed distance is at most (D + 4) u (L + diagonal) below its
+// exact distance, itself >= L; so a skipped entry's members all have computed
+// distances above max(thr, 0), and none attains or ties the minimum.  Inside
+// the stored box the computed distance is exactly 0 (every clamped
+// difference rounds to a value <= 0) and the entry passes.  A NaN walker
+// gives distance 0 or NaN and passes.
+template <int D>
+__device__ __forceinline__ void box_round(const float* __restrict__ cb, int n_cl, const uint32_t* queue, int base,
+                                          int count, const float (&x)[D], float thr, uint32_t* mq, int& mqn)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const bool act = lane < count;
+    const uint32_t e = act ? queue[base + lane] : 0u;
+    const int w = entry_walker(e);
+    int c = (int)(e >> 6);
+    c = c < n_cl ? c : n_cl - 1;  // an entry never points past the table
+    float xw[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) xw[i] = __shfl(x[i], w, kWave);
+    const float tw = __builtin_fmaxf(__shfl(thr, w, kWave), 0.0f);
+    const mf4* r = reinterpret_cast<const mf4*>(cb + (int64_t)c * kClusterBox);
+    const mf4 lo0 = r[0], hi0 = r[2];
+    mf4 lo1 = lo0, hi1 = hi0;
+    if (D > 4) {
+        lo1 = r[1];
+        hi1 = r[3];
+    }
+    float acc = 0.0f;
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        const float lo = i < 4 ? lo0[i & 3] : lo1[i & 3];
+        const float hi = i < 4 ? hi0[i & 3] : hi1[i & 3];
+        const float t = __builtin_fmaxf(__builtin_fmaxf(lo - xw[i], xw[i] - hi), 0.0f);
+        acc = __builtin_fmaf(t, t, acc);
+    }
+    const bool pass = act && !(__builtin_amdgcn_sqrtf(acc) * Cull<float>::shrink > tw);
+    const uint64_t m = __ballot(pass);
+    if (pass) {
+        const uint32_t rank =
+            __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+        mq[mqn + (int)rank] = e;
+    }
+    mqn += __popcll(m);
 }
 
 // Inclusive prefix sum over the 64 lanes of a wave: DPP row shifts by 1, 2,
@@ -542,25 +605,28 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v)
 }
 
 // Min over the members of the clusters each lane may need (thr as for
-// cluster_min), with the cluster test on the matrix cores and the members
+// cluster_min), with the cluster test on the matrix cores, a bounding-box
+// test of the pairs it keeps, and the members of the pairs that pass both
 // scanned pair by pair.  Requires every lane of the wave to be active; lds is
-// the wave's kPairLds-word slice (queue, then minima).  evals: member
-// distances evaluated by the wave.
+// the wave's kPairLds-word slice (first queue, member queue, minima).  evals:
+// member distances evaluated by the wave; boxes: bounding boxes tested.
 //
 // Per tile each lane gathers its 16 needs (bit 4 rt + r: walker 16 rt + 4 g +
 // r, g = lane / 16, needs cluster 16 t + lane % 16) into one mask; a wave
 // prefix sum of the popcounts gives every lane its queue slots, so a tile's
 // pairs are queued in one pass.  A tile whose pairs would overflow the queue
-// first evaluates the pairs already waiting, then goes row tile by row tile
-// (at most 4 x 64 pairs each).
+// first tests the pairs already waiting, then goes two need bits at a time
+// (at most 128 pairs each).
 template <int D, bool BOX>
-__device__ __forceinline__ float cluster_min_pairs(cptr<float> rows, const float* __restrict__ mf, int n_cl,
-                                                   const float (&x)[D], float thr, bool live, uint64_t& evals,
+__device__ __forceinline__ float cluster_min_pairs(cptr<float> rows, const float* __restrict__ mf,
+                                                   const float* __restrict__ cb, int n_cl, const float (&x)[D],
+                                                   float thr, bool live, uint64_t& evals, uint64_t& boxes,
                                                    uint32_t* lds)
 {
     const int lane = threadIdx.x & (kWave - 1);
     uint32_t* queue = lds;
-    uint32_t* best = lds + kPairCap;
+    uint32_t* mq = lds + kPairCap;
+    uint32_t* best = mq + kBoxQueue;
     best[lane] = ord_of(Math<float>::inf());
     float A[3][4];
     mfma_walker_operands<D>(x, thr, live, A);
@@ -571,8 +637,20 @@ __device__ __forceinline__ float cluster_min_pairs(cptr<float> rows, const float
     // q = (bit << 2) | g = 16 rt + 4 r + g, so each entry is one shift-or of
     // the bit index into the lane's constant part
     const uint32_t lane_e = ((uint32_t)(lane & (kMfmaTile - 1)) << 6) | (uint32_t)(lane >> 4);
-    int qn = 0;  // queued pairs (wave-uniform), < 64 between tiles
-    uint32_t pairs = 0;
+    int qn = 0;   // first-queue pairs (wave-uniform), < 64 between tiles
+    int mqn = 0;  // member-queue pairs (wave-uniform), < 64 between rounds
+    uint32_t tested = 0, pairs = 0;
+    // box-test first-queue entries [base, base + count); a full member queue
+    // evaluates its last 64
+    auto test_round = [&](int base, int count) {
+        box_round<D>(cb, n_cl, queue, base, count, x, thr, mq, mqn);
+        tested += (uint32_t)count;
+        if (mqn >= kWave) {
+            mqn -= kWave;
+            pairs += kWave;
+            pair_round<D, BOX>(rows, n_cl, mq, mqn, kWave, x, best);
+        }
+    };
     // the next tile's features load while this tile is tested and queued (the
     // table ends with a spare tile that is never used)
     mf4 bn = tab[0];
@@ -600,14 +678,13 @@ __device__ __forceinline__ float cluster_min_pairs(cptr<float> rows, const float
         uint32_t chunk = 0xFFFFu;  // the needs queued in this pass
         if (qn + total > kPairCap) {
             if (qn > 0) {
-                pair_round<D, BOX>(rows, n_cl, queue, 0, qn, x, best);
-                pairs += (uint32_t)qn;
+                test_round(0, qn);
                 qn = 0;
             }
-            chunk = 0xFu;
+            chunk = 0x3u;
         }
         const uint32_t tile_e = (uint32_t)(t * kMfmaTile) << 6;
-        for (;;) {  // wave-uniform: one pass, or one per row tile
+        for (;;) {  // wave-uniform: one pass, or one per two need bits
             uint32_t m = nm & chunk;
             if (chunk != 0xFFFFu) {
                 cnt = (uint32_t)__builtin_popcount(m);
@@ -623,15 +700,25 @@ __device__ __forceinline__ float cluster_min_pairs(cptr<float> rows, const float
             qn += total;
             while (qn >= kWave) {  // the last 64 queued go first
                 qn -= kWave;
-                pairs += kWave;
-                pair_round<D, BOX>(rows, n_cl, queue, qn, kWave, x, best);
+                test_round(qn, kWave);
             }
             if (chunk & 0x8000u) break;
-            chunk <<= 4;
+            chunk <<= 2;
         }
     }
-    if (qn > 0) pair_round<D, BOX>(rows, n_cl, queue, 0, qn, x, best);
-    evals += ((uint64_t)pairs + (uint64_t)qn) * kCluster;
+    // the step's last pairs: when the waiting ones of both queues fit one
+    // member round, they go together without their box test (that round runs
+    // anyway unless every box test fails, and a skipped test only adds member
+    // distances, which never change the minimum)
+    if (qn + mqn <= kWave) {
+        if (lane < qn) mq[mqn + lane] = queue[lane];
+        mqn += qn;
+    } else {
+        test_round(0, qn);
+    }
+    if (mqn > 0) pair_round<D, BOX>(rows, n_cl, mq, 0, mqn, x, best);
+    evals += ((uint64_t)pairs + (uint64_t)mqn) * kCluster;
+    boxes += tested;
     return float_of_ord(best[lane]);
 }
 
@@ -667,13 +754,14 @@ __device__ __forceinline__ T distance(cenv<T> p, const T (&x)[D], int& cls, Work
     T db;
     uint32_t nb, ns;         // member distances per lane (wave-uniform scans)
     uint64_t eb = 0, es = 0;  // member distances of the wave (pair-compacted scans)
+    uint64_t cbt = 0;         // cluster bounding boxes tested by the wave
     if (p->n_cl_box) {
         nb = 0;
         bool done = false;
         if constexpr (sizeof(T) == 4) {
             if (p->use_mfma == 2) {
-                db = cluster_min_pairs<D, true>(to_const(p->box_cl), fresh(p)->box_mf, fresh(p)->n_cl_box, xg,
-                                                dga, live, eb, wc.pairs);
+                db = cluster_min_pairs<D, true>(to_const(p->box_cl), fresh(p)->box_mf, fresh(p)->box_cb,
+                                                fresh(p)->n_cl_box, xg, dga, live, eb, cbt, wc.pairs);
                 done = true;
             } else if (p->use_mfma) {
                 db = cluster_min_mfma<D, true>(to_const(p->box_cl), fresh(p)->box_mf, fresh(p)->n_cl_box, xg,
@@ -695,8 +783,9 @@ __device__ __forceinline__ T distance(cenv<T> p, const T (&x)[D], int& cls, Work
         bool done = false;
         if constexpr (sizeof(T) == 4) {
             if (p->use_mfma == 2) {
-                ds = cluster_min_pairs<D, false>(to_const(p->sph_cl), fresh(p)->sph_mf, fresh(p)->n_cl_sph, xg,
-                                                 Math<T>::min(dga, db), live, es, wc.pairs);
+                ds = cluster_min_pairs<D, false>(to_const(p->sph_cl), fresh(p)->sph_mf, fresh(p)->sph_cb,
+                                                 fresh(p)->n_cl_sph, xg, Math<T>::min(dga, db), live, es, cbt,
+                                                 wc.pairs);
                 done = true;
             } else if (p->use_mfma) {
                 ds = cluster_min_mfma<D, false>(to_const(p->sph_cl), fresh(p)->sph_mf, fresh(p)->n_cl_sph, xg,
@@ -714,6 +803,7 @@ __device__ __forceinline__ T distance(cenv<T> p, const T (&x)[D], int& cls, Work
     const uint64_t lanes = (uint64_t)__popcll(__ballot(live));
     wc.sph += lanes * ns + es;
     wc.box += lanes * nb + eb;
+    wc.cbox += cbt;
     const T ao = Math<T>::min(da, dout);
     const T bo = Math<T>::min(db, ao);
     const T rest = Math<T>::min(ds, bo);

@@ -107,15 +107,24 @@ __device__ __forceinline__ void add_work(double (&a)[N], int at, const WorkCount
     if ((threadIdx.x & (kWave - 1)) == 0) {
         a[at] += (double)wc.sph;
         a[at + 1] += (double)wc.box;
+        a[at + 2] += (double)wc.cbox;
     }
 }
 
 // ------------------------------------------------------------------------
-// Plain kernel.  FP32: at least 3 waves per SIMD (at most 168 registers per
-// lane); left free, the allocator may take a few more and fall to 2.
+// Plain kernel.  FP32: at least 4 waves per SIMD (at most 128 registers per
+// lane) where that needs no scratch memory (d <= 6, and d = 7 without a
+// point source), else at least 3 (168 registers); left free, the allocator
+// may take a few more and fall a wave lower.
 // ------------------------------------------------------------------------
+template <typename T, int D, bool SRC>
+constexpr int plain_waves()
+{
+    return sizeof(T) != 4 ? 1 : (D < 7 || (D == 7 && !SRC)) ? 4 : 3;
+}
+
 template <typename T, int D, bool BWD, bool SRC>
-__global__ void __launch_bounds__(kBlock, sizeof(T) == 4 ? 3 : 1)
+__global__ void __launch_bounds__(kBlock, (plain_waves<T, D, SRC>()))
 plain_kernel(const EnvP<T>* penv, const T* __restrict__ queries, int64_t n_units, int32_t chunks,
              int64_t n_walks, int64_t w_base, uint32_t q_base, const uint64_t* __restrict__ key_add,
              double* __restrict__ partials, double* __restrict__ records)
@@ -331,8 +340,9 @@ __device__ __forceinline__ void run_unit(cenv<float> p, CBatch& be, int64_t loca
     for (int i = 0; i < kMaxDim; ++i) xq[i] = (i < d) ? qrow[i < d ? i : 0] : 0.0f;
 
     // registers: [0] u, [1] u^2, then steps, truncated, degenerate, u S,
-    // goal weight, sphere and box distances (the nacc layout without the
-    // gradient entries; the last two from the wave's work tally)
+    // goal weight, sphere and box distances and cluster boxes (the nacc
+    // layout without the gradient entries; the last three from the wave's
+    // work tally)
     constexpr int NR = kNAccBatch - kLdsAcc;
     double a[NR];
 #pragma unroll
@@ -517,6 +527,7 @@ finalize_batch(const BatchEnv* __restrict__ benv, const double* __restrict__ par
             st[M + 4] = a[7 + 2 * M] / n;                    // sphere distances per walk
             st[M + 5] = a[8 + 2 * M] / n;                    // box distances per walk
             st[M + 6] = (a[2 + 2 * M] / n) * (double)be.n_cl;  // cluster bounds per walk
+            st[M + 7] = a[9 + 2 * M] / n;                    // cluster boxes per walk
         }
         if (BWD) {
             const double ub = (double)ubar[qg];

@@ -10,7 +10,7 @@ constexpr int kMaxTerms = 96;      // Horner terms of the 0F1 weight series
 constexpr int kBatchStride = 8;    // row stride of batched query / gradient arrays
 constexpr int kWave = 64;          // CDNA wavefront width
 constexpr uint32_t kDefaultMaxSteps = 1u << 16;
-constexpr int kBatchStats = 15;    // columns of a batched stats row
+constexpr int kBatchStats = 16;    // columns of a batched stats row
 
 enum Class : int32_t { kGoal = 0, kSphere = 1, kBox = 2, kOuter = 3, kArm = 4 };
 enum Status : int32_t { kAbsorbed = 0, kDegenerate = 1, kTruncated = 2 };
@@ -45,12 +45,24 @@ constexpr int kClusterMin = 64;
 // clusters of the last tile, and one spare tile after it, have feature
 // 9 = 1e30 (always skipped).
 // Pair-compacted member scan: (walker, cluster) pairs that the matrix-core
-// test keeps are queued per wave in LDS and evaluated 64 at a time, one pair
-// per lane.  Between tiles fewer than 64 pairs wait; a tile adds its pairs in
-// one pass when they fit, else one row tile (at most 256) at a time after
-// the waiting ones are evaluated, so 320 entries never overflow.
-constexpr int kPairCap = 320;
-constexpr int kPairLds = kPairCap + kWave;  // pair-scan LDS words per wave: queue, then minima
+// test keeps are queued per wave in LDS and taken 64 at a time, one pair per
+// lane, through a second test against the cluster's bounding box; the pairs
+// that pass go to a member queue and are evaluated 64 at a time (a step's
+// last pairs join its last member round untested when they fit).  Between
+// tiles fewer than 64 pairs wait in the first queue; a tile adds its pairs in
+// one pass when they fit, else two need bits of every lane (at most 128
+// pairs) at a time after the waiting ones are tested, so 256 entries never
+// overflow.  The member queue holds fewer than 64 between rounds and gains
+// at most 64 per round.
+constexpr int kPairCap = 256;
+constexpr int kBoxQueue = 2 * kWave;
+// pair-scan LDS words per wave: first queue, member queue, then minima
+constexpr int kPairLds = kPairCap + kBoxQueue + kWave;
+
+// Cluster bounding boxes (FP32 kernels): per cluster lo[kMaxDim] then
+// hi[kMaxDim] (zero past d), the box of the members enlarged by a margin
+// (see build_cluster_boxes) and rounded outwards.
+constexpr int kClusterBox = 2 * kMaxDim;
 
 constexpr int kMfmaTile = 16;
 constexpr int kMfmaFeat = 12;
@@ -67,6 +79,8 @@ struct EnvP {
     const T* box_bnd;      // n_cl_box + 1 bounding spheres, sph_stride(d) each (last: unused)
     const float* sph_mf;   // matrix-core cluster features, (ceil(n_cl_sph / 16) + 1) x 64 x 4 (FP32 only)
     const float* box_mf;
+    const float* sph_cb;   // n_cl_sph x kClusterBox cluster bounding boxes (FP32 only)
+    const float* box_cb;
     int32_t n_sph, n_box;
     int32_t n_cl_sph, n_cl_box;  // 0: scan the caller-order table instead
     int32_t use_mfma, pad_mf;    // FP32 cluster tests: 0 vector ALUs, 1 matrix cores with a
@@ -119,7 +133,8 @@ struct BatchEnv {
 // [0] sum u, [1] sum u^2, [2, 2+d) sum grad, [2+d, 2+2d) sum grad^2,
 // [2+2d] sum steps, [3+2d] truncated, [4+2d] degenerate,
 // [5+2d] sum u*S (d u/d sigma), [6+2d] sum W 1{goal} (d u/d g_goal),
-// [7+2d] sphere distances evaluated, [8+2d] box distances evaluated.
-__host__ __device__ constexpr int nacc(int d) { return 9 + 2 * d; }
+// [7+2d] sphere distances evaluated, [8+2d] box distances evaluated,
+// [9+2d] cluster bounding boxes tested.
+__host__ __device__ constexpr int nacc(int d) { return 10 + 2 * d; }
 
 }  // namespace wos

@@ -206,7 +206,8 @@ def test_binding_constants_match_the_header(B):
     shared = [k for k in defs if hasattr(B, k)]
     assert {"WOS_FP64", "WOS_FULL_SCAN", "WOS_SCALAR_CULL", "WOS_WAVE_SCAN", "WOS_OUT_FP64",
             "WOS_EINVAL", "WOS_ENOTSUP", "WOS_OUTER_BOX", "WOS_NOALLOC_SCRATCH_BYTES",
-            "WOS_NOALLOC_MAX_ENVS", "WOS_CLUSTER_ROWS"} <= set(shared)
+            "WOS_NOALLOC_MAX_ENVS", "WOS_CLUSTER_ROWS", "WOS_BATCH_STATS",
+            "WOS_BATCH_STRIDE"} <= set(shared)
     for k in shared:
         assert int(defs[k]) == getattr(B, k), k
 

@@ -148,6 +148,120 @@ def test_cull_test_is_sound_in_fp32(B):
             assert worst > 0, (name, kind, worst)
 
 
+def _box_lb32(x, lohi, d):
+    """The bounding-box test value as the FP32 kernels form it: per axis
+    max(lo - x, x - hi, 0), the squares summed by fused multiply-adds, the
+    square root, times 1 - 2^-16."""
+    lo = lohi[:, :d].astype(np.float32)
+    hi = lohi[:, d:].astype(np.float32)
+    acc = np.zeros((len(x), len(lo)), np.float32)
+    for i in range(d):
+        a = (lo[None, :, i] - x[:, None, i]).astype(np.float32)
+        b = (x[:, None, i] - hi[None, :, i]).astype(np.float32)
+        t = np.maximum(np.maximum(a, b), np.float32(0))
+        acc = (t.astype(np.float64) * t + acc).astype(np.float32)   # fma
+    return (np.sqrt(acc).astype(np.float32) * np.float32(1.0 - 2.0 ** -16)).astype(np.float32)
+
+
+def _members(s, kind):
+    """FP32 member rows of one kind and the per-axis half extent of each
+    member (radius for spheres, half-widths for boxes), in FP64."""
+    if kind == "sph":
+        c = np.asarray(s["sph_c"], np.float32)
+        r = np.asarray(s["sph_r"], np.float32)
+        return c, r, np.repeat(r.astype(np.float64)[:, None], c.shape[1], axis=1)
+    c = np.asarray(s["box_c"], np.float32)
+    h = np.asarray(s["box_h"], np.float32)
+    return c, h, h.astype(np.float64)
+
+
+def test_cluster_boxes_hold_their_members_with_margin(B):
+    """Every cluster box contains its members' box enlarged by 2^-16 of that
+    box's diagonal on every side (lo and hi as the FP32 device table holds
+    them); the boxes are listed in the cluster order of wos_debug_clusters."""
+    for name, s in _sets() + _far_tight_sets():
+        d = s["d"]
+        out = B.wos_debug_clusters(d, s["sph_c"], s["sph_r"], s["box_c"], s["box_h"])
+        boxes = B.wos_debug_cluster_boxes(d, s["sph_c"], s["sph_r"], s["box_c"], s["box_h"])
+        for kind in ("sph", "box"):
+            order, bnd = out[kind]
+            lohi = boxes[kind]
+            assert lohi.shape == (len(bnd), 2 * d), (name, kind)
+            if len(order) == 0:
+                continue
+            c, _, ext = _members(s, kind)
+            assert np.array_equal(lohi.astype(np.float32).astype(np.float64), lohi)
+            for g in range(len(bnd)):
+                m = order[g * CL:(g + 1) * CL]
+                m = m[m >= 0]
+                lo = (c[m].astype(np.float64) - ext[m]).min(0)
+                hi = (c[m].astype(np.float64) + ext[m]).max(0)
+                delta = np.sqrt(((hi - lo) ** 2).sum()) * 2.0 ** -16
+                assert np.all(lohi[g, :d] <= lo - delta), (name, kind, g)
+                assert np.all(lohi[g, d:] >= hi + delta), (name, kind, g)
+
+
+def test_box_test_is_sound_in_fp32(B):
+    """Wherever the FP32 bounding-box value of a cluster is positive, every
+    member's FP32 distance is at least that value, so a pair skipped because
+    the value exceeds max(thr, 0) has no member at or below thr.  Probes lie
+    on, just off and inside members, just outside the faces and corners of
+    the cluster boxes, and uniformly in the outer box."""
+    rng = np.random.default_rng(12)
+    for name, s in _sets() + _far_tight_sets():
+        d = s["d"]
+        out = B.wos_debug_clusters(d, s["sph_c"], s["sph_r"], s["box_c"], s["box_h"])
+        boxes = B.wos_debug_cluster_boxes(d, s["sph_c"], s["sph_r"], s["box_c"], s["box_h"])
+        for kind in ("sph", "box"):
+            order, _ = out[kind]
+            lohi = boxes[kind]
+            if len(order) == 0:
+                continue
+            c, r_or_h, ext = _members(s, kind)
+            rad = np.sqrt((ext ** 2).sum(1)) if kind == "box" else ext[:, 0]
+            x = _probe_points(rng, c.astype(np.float64), rad, d, 800)
+            g = rng.integers(0, len(lohi), 800)
+            # just outside a face or a corner of a cluster box
+            side = rng.integers(0, 2, size=(800, d))
+            corner = np.where(side, lohi[g, d:], lohi[g, :d])
+            face = rng.uniform(lohi[g, :d], lohi[g, d:])
+            ax = rng.integers(0, d, 800)
+            face[np.arange(800), ax] = corner[np.arange(800), ax]
+            off = rng.choice([0.0, 1e-7, 1e-5, 1e-3], size=(800, 1))
+            push = np.where(side, 1.0, -1.0) * off
+            x = np.concatenate([x, corner + push, face + push]).astype(np.float32)
+            dist = _sphere_d32(x, c, r_or_h) if kind == "sph" else _box_d32(x, c, r_or_h)
+            lb = _box_lb32(x, lohi, d)
+            worst = np.inf
+            for k in range(len(lohi)):
+                m = order[k * CL:(k + 1) * CL]
+                m = m[m >= 0]
+                pos = lb[:, k] > 0
+                if pos.any():
+                    gap = dist[pos][:, m].min(1).astype(np.float64) - lb[pos, k]
+                    worst = min(worst, gap.min())
+            assert worst >= 0, (name, kind, worst)
+
+
+def test_box_test_tightens_the_sphere_bound(B):
+    """On the 7-D segment workload the walker's threshold is mostly the
+    outer-box distance; of the (query, cluster) pairs whose bounding sphere
+    comes within that threshold, the bounding box rules out most."""
+    s = S.scene_c3(n_walks=16)
+    d = s["d"]
+    out = B.wos_debug_clusters(d, s["sph_c"], s["sph_r"])
+    lohi = B.wos_debug_cluster_boxes(d, s["sph_c"], s["sph_r"])["sph"]
+    _, bnd = out["sph"]
+    x = np.asarray(s["queries"], np.float32)
+    thr = np.minimum(np.pi - np.abs(x.astype(np.float64)).max(1),
+                     np.linalg.norm(x - s["goal_c"], axis=1) - s["goal_r"])
+    sphere_lb = np.linalg.norm(x[:, None].astype(np.float64) - bnd[None, :, :-1], axis=2) - bnd[None, :, -1]
+    kept = sphere_lb <= thr[:, None]
+    box_out = _box_lb32(x, lohi, d) > thr[:, None]
+    assert kept.sum() > 0
+    assert (kept & box_out).sum() > 0.5 * kept.sum()
+
+
 def test_cull_test_is_sound_in_fp64(B):
     shrink = 1.0 - 2.0 ** -45
     rng = np.random.default_rng(4)

@@ -414,7 +414,7 @@ def gpu_batch(B, envs, n_walks, seed, ubar=None, torch_dtype=None, full_scan=Fal
     n = int(off[-1])
     u = torch.empty(n, device="cuda")
     g = torch.empty(n, 8, device="cuda")
-    st = torch.empty(n, 15, dtype=torch.float64, device="cuda")
+    st = torch.empty(n, B.BATCH_STATS, dtype=torch.float64, device="cuda")
     kw = {}
     if ubar is not None:
         kw = dict(grad_u=dev(ubar, torch.float32), out_dx=torch.empty(n, 8, device="cuda"),
@@ -484,7 +484,9 @@ def test_culling_changes_no_result_plain(B, fp64):
 def test_culling_changes_no_result_batch(B):
     """Same in the persistent kernel, and the work columns of the stats
     count what the scans did: a full scan evaluates M obstacles per step, a
-    culled one at most that plus one bound per cluster."""
+    culled one at most that plus one bound per cluster, and at most one
+    bounding-box test per cluster and step (made only for pairs the cluster
+    bound keeps)."""
     envs = _ragged(n_envs=12, q_cap=16, n_walks=256)
     rng = np.random.default_rng(9)
     ubar = rng.normal(size=sum(len(e["queries"]) for e in envs)).astype(np.float32)
@@ -499,12 +501,13 @@ def test_culling_changes_no_result_batch(B):
         M = len(s["sph_r"])
         steps = b["st"][sl, 9]
         assert np.allclose(b["st"][sl, 12], steps * M, rtol=1e-12)
-        assert np.all(b["st"][sl, 13] == 0) and np.all(b["st"][sl, 14] == 0)
+        assert np.all(b["st"][sl, 13] == 0) and np.all(b["st"][sl, 14] == 0) and np.all(b["st"][sl, 15] == 0)
         if M < 64:
             assert np.array_equal(a["st"][sl, 12:], b["st"][sl, 12:]), e
         else:
             assert np.allclose(a["st"][sl, 14], steps * -(-M // 8), rtol=1e-12)
             assert np.all(a["st"][sl, 12] <= (-(-M // 8) * 8) * steps * (1 + 1e-12))
+            assert np.all(a["st"][sl, 15] <= -(-M // 8) * steps * (1 + 1e-12))
             saved += (b["st"][sl, 12] - a["st"][sl, 12]).sum()
             done += (a["st"][sl, 12] + a["st"][sl, 14]).sum()
             full += b["st"][sl, 12].sum()
@@ -882,7 +885,7 @@ def _fused_full_launch(B, envs):
     q = dev(qp, torch.float32)
     u = torch.empty(n, device="cuda")
     g = torch.empty(n, 8, device="cuda")
-    st = torch.empty(n, 15, dtype=torch.float64, device="cuda")
+    st = torch.empty(n, B.BATCH_STATS, dtype=torch.float64, device="cuda")
     ubar = torch.ones(n, device="cuda")
     dx = torch.empty(n, 8, device="cuda")
     ds = torch.empty(len(envs), dtype=torch.float64, device="cuda")

@@ -33,7 +33,7 @@ def _batch(B, envs, noalloc, bwd, seed=11):
     # outputs start as NaN so that a row the call does not write shows up
     u = torch.full((n,), float("nan"), device="cuda")
     g = torch.full((n, 8), float("nan"), device="cuda")
-    st = torch.full((n, 15), float("nan"), dtype=torch.float64, device="cuda")
+    st = torch.full((n, B.BATCH_STATS), float("nan"), dtype=torch.float64, device="cuda")
     kw = {}
     if bwd:
         ub = torch.as_tensor(np.random.default_rng(3).normal(size=n).astype(np.float32), device="cuda")
@@ -78,7 +78,7 @@ def test_noalloc_matches_the_allocating_call_twice(B):
 
 
 def test_noalloc_rejects_a_batch_beyond_its_array(B):
-    """400000 queries of 64 walks are 400000 work units of 200 bytes: more
+    """400000 queries of 64 walks are 400000 work units of 208 bytes: more
     than the 64 MiB array; the call returns WOS_EINVAL and writes nothing."""
     import torch
     s = S.scene_spheres(3, n_queries=1, n_walks=64, seed=1)
