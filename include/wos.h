@@ -76,6 +76,13 @@ extern "C" {
 #define WOS_OUT_FP64 16u   /* wos_estimate with FP32 walks: out_u and out_grad are
                               double, the FP64 walk sums without rounding to FP32
                               (means below FP32's range stay); other calls reject it */
+#define WOS_NO_BOX_TEST 32u /* FP32 pair scan: every (walker, cluster) pair the
+                               cluster bound keeps has its members scanned, without
+                               the bounding-box test; same walks.  By default the
+                               box test runs where the obstacles depend on 6 or
+                               more coordinates (it culls little below that) */
+#define WOS_BOX_TEST 64u    /* FP32 pair scan: the bounding-box test in every
+                               dimension; same walks (not with WOS_NO_BOX_TEST) */
 
 /* boundary-data modes */
 #define WOS_BDATA_CLASS 0  /* g_goal / g_obstacle / g_outer per component */

@@ -20,6 +20,8 @@ LIB_PATH = os.path.join(PKG, "libwos.so")
 WOS_OK, WOS_EINVAL, WOS_EDIM, WOS_ENOMEM, WOS_EHIP, WOS_ENOTSUP = 0, -1, -2, -3, -4, -5
 WOS_FP32, WOS_FP64, WOS_FULL_SCAN, WOS_SCALAR_CULL, WOS_WAVE_SCAN = 0, 1, 2, 4, 8
 WOS_OUT_FP64 = 16
+WOS_NO_BOX_TEST = 32
+WOS_BOX_TEST = 64
 WOS_NOALLOC_SCRATCH_BYTES = 64 << 20
 WOS_NOALLOC_MAX_ENVS = 1024
 WOS_CLUSTER_ROWS = 8  # obstacle rows per cluster (wos_debug_clusters capacities)
@@ -165,10 +167,11 @@ def _stream(stream=None):
 
 
 def options(fp64=False, env_id=0, max_steps=0, full_scan=False, scalar_cull=False, wave_scan=False,
-            out_fp64=False):
+            out_fp64=False, no_box_test=False, box_test=False):
     flags = (WOS_FP64 if fp64 else WOS_FP32) | (WOS_FULL_SCAN if full_scan else 0) | \
         (WOS_SCALAR_CULL if scalar_cull else 0) | (WOS_WAVE_SCAN if wave_scan else 0) | \
-        (WOS_OUT_FP64 if out_fp64 else 0)
+        (WOS_OUT_FP64 if out_fp64 else 0) | (WOS_NO_BOX_TEST if no_box_test else 0) | \
+        (WOS_BOX_TEST if box_test else 0)
     return Options(flags, int(env_id), int(max_steps), 0)
 
 

@@ -179,6 +179,7 @@ int make_env(const wos_domain* D, double sigma, double eps, uint64_t seed, uint3
     p.sph_cb = D->cl_f ? D->cl_f + D->off_sph_cb : nullptr;
     p.box_cb = D->cl_f ? D->cl_f + D->off_box_cb : nullptr;
     p.use_mfma = (sizeof(T) != 4 || (o.flags & WOS_SCALAR_CULL)) ? 0 : (o.flags & WOS_WAVE_SCAN) ? 1 : 2;
+    p.box_test = (o.flags & WOS_BOX_TEST) ? 1 : (o.flags & WOS_NO_BOX_TEST) ? 0 : D->geom_d >= kBoxTestMinDim;
     // a pair-queue entry holds the cluster index in 26 bits
     if (p.use_mfma == 2 && (D->n_cl_sph >= (1 << 26) || D->n_cl_box >= (1 << 26))) p.use_mfma = 1;
     p.d = D->d;
@@ -530,7 +531,10 @@ int read_opts(const wos_options* opt, wos_options& o)
 {
     o = wos_options{WOS_FP32, 0u, 0u, 0u};
     if (opt) o = *opt;
-    if (o.flags & ~(WOS_FP64 | WOS_FULL_SCAN | WOS_SCALAR_CULL | WOS_WAVE_SCAN | WOS_OUT_FP64))
+    if ((o.flags & WOS_BOX_TEST) && (o.flags & WOS_NO_BOX_TEST))
+        return fail(WOS_EINVAL, "WOS_BOX_TEST and WOS_NO_BOX_TEST together");
+    if (o.flags & ~(WOS_FP64 | WOS_FULL_SCAN | WOS_SCALAR_CULL | WOS_WAVE_SCAN | WOS_OUT_FP64 | WOS_NO_BOX_TEST |
+                    WOS_BOX_TEST))
         return fail(WOS_EINVAL, "unknown flags 0x%x", o.flags);
     if (o.reserved != 0) return fail(WOS_EINVAL, "wos_options.reserved must be 0");
     return WOS_OK;

@@ -59,6 +59,11 @@ constexpr int kBoxQueue = 2 * kWave;
 // pair-scan LDS words per wave: first queue, member queue, then minima
 constexpr int kPairLds = kPairCap + kBoxQueue + kWave;
 
+// The bounding-box test runs by default where the obstacles depend on at
+// least kBoxTestMinDim coordinates: below that a cluster's bounding sphere is
+// nearly as tight as its box, and the test costs more than it saves.
+constexpr int kBoxTestMinDim = 6;
+
 // Cluster bounding boxes (FP32 kernels): per cluster lo[kMaxDim] then
 // hi[kMaxDim] (zero past d), the box of the members enlarged by a margin
 // (see build_cluster_boxes) and rounded outwards.
@@ -83,8 +88,9 @@ struct EnvP {
     const float* box_cb;
     int32_t n_sph, n_box;
     int32_t n_cl_sph, n_cl_box;  // 0: scan the caller-order table instead
-    int32_t use_mfma, pad_mf;    // FP32 cluster tests: 0 vector ALUs, 1 matrix cores with a
-                                 // wave-uniform member scan, 2 matrix cores with pair compaction
+    int32_t use_mfma, box_test;  // FP32 cluster tests: 0 vector ALUs, 1 matrix cores with a
+                                 // wave-uniform member scan, 2 matrix cores with pair compaction;
+                                 // box_test (with 2): pairs pass the bounding-box test first
     int32_t d, has_goal;
     int32_t geom_d, pad_g;     // obstacles and the outer boundary depend on x[0..geom_d) only
     const T* arm_pts;          // planar arm: n_arm x 2 task-plane obstacle points

@@ -204,7 +204,7 @@ def test_binding_constants_match_the_header(B):
     src = open(HEADER).read()
     defs = dict(re.findall(r"^#define\s+(WOS_[A-Z0-9_]+)\s+\(?(-?\d+)u?\)?", src, flags=re.M))
     shared = [k for k in defs if hasattr(B, k)]
-    assert {"WOS_FP64", "WOS_FULL_SCAN", "WOS_SCALAR_CULL", "WOS_WAVE_SCAN", "WOS_OUT_FP64",
+    assert {"WOS_FP64", "WOS_FULL_SCAN", "WOS_SCALAR_CULL", "WOS_WAVE_SCAN", "WOS_OUT_FP64", "WOS_NO_BOX_TEST", "WOS_BOX_TEST",
             "WOS_EINVAL", "WOS_ENOTSUP", "WOS_OUTER_BOX", "WOS_NOALLOC_SCRATCH_BYTES",
             "WOS_NOALLOC_MAX_ENVS", "WOS_CLUSTER_ROWS", "WOS_BATCH_STATS",
             "WOS_BATCH_STRIDE"} <= set(shared)
@@ -213,11 +213,15 @@ def test_binding_constants_match_the_header(B):
 
 
 def test_option_flags_are_checked_before_device_work(B):
-    """Unknown flag bits are rejected; the read-out, which takes u as given,
-    rejects WOS_OUT_FP64 (it applies to wos_estimate only)."""
+    """Unknown flag bits, and the box test both forced on and off, are
+    rejected; the read-out, which takes u as given, rejects WOS_OUT_FP64 (it
+    applies to wos_estimate only)."""
     opt = B.Options(1 << 10, 0, 0, 0)
     assert B.lib.wos_varadhan(None, None, 0, 2, 2, 1.0, None, None, C.byref(opt), None) == B.WOS_EINVAL
     assert b"unknown flags" in B.lib.wos_last_error()
+    opt = B.options(box_test=True, no_box_test=True)
+    assert B.lib.wos_varadhan(None, None, 0, 2, 2, 1.0, None, None, C.byref(opt), None) == B.WOS_EINVAL
+    assert b"together" in B.lib.wos_last_error()
     opt = B.options(out_fp64=True)
     assert B.lib.wos_varadhan(None, None, 0, 2, 2, 1.0, None, None, C.byref(opt), None) == B.WOS_ENOTSUP
 

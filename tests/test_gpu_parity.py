@@ -31,7 +31,8 @@ def dev(a, dtype):
 
 
 def gpu_estimate(B, scene, fp64=False, queries=None, n_walks=None, seed=None, env_id=0,
-                 max_steps=0, sigma=None, eps=None, full_scan=False, scalar_cull=False, wave_scan=False):
+                 max_steps=0, sigma=None, eps=None, full_scan=False, scalar_cull=False, wave_scan=False,
+                 no_box_test=False, box_test=False):
     import torch
     dt = torch.float64 if fp64 else torch.float32
     dom = B.Domain(scene)
@@ -44,7 +45,7 @@ def gpu_estimate(B, scene, fp64=False, queries=None, n_walks=None, seed=None, en
                    scene["sigma"] if sigma is None else sigma, scene["eps"] if eps is None else eps,
                    scene["seed"] if seed is None else seed, u, g, st,
                    opt=B.options(fp64, env_id, max_steps, full_scan=full_scan, scalar_cull=scalar_cull,
-                                 wave_scan=wave_scan))
+                                 wave_scan=wave_scan, no_box_test=no_box_test, box_test=box_test))
     torch.cuda.synchronize()
     return u.cpu().numpy().astype(np.float64), g.cpu().numpy().astype(np.float64), st.cpu().numpy()
 
@@ -402,7 +403,7 @@ def _ragged(n_envs=10, q_cap=24, n_walks=512):
 
 
 def gpu_batch(B, envs, n_walks, seed, ubar=None, torch_dtype=None, full_scan=False, scalar_cull=False,
-              wave_scan=False):
+              wave_scan=False, no_box_test=False, box_test=False):
     import torch
     doms = [B.Domain(e) for e in envs]
     Qs = [len(e["queries"]) for e in envs]
@@ -422,7 +423,8 @@ def gpu_batch(B, envs, n_walks, seed, ubar=None, torch_dtype=None, full_scan=Fal
                   out_dg=torch.empty(len(envs), dtype=torch.float64, device="cuda"))
     B.wos_estimate_batch(doms, q, off, [e["sigma"] for e in envs], [e["eps"] for e in envs], n_walks,
                          seed, u, g, st, opt=B.options(full_scan=full_scan, scalar_cull=scalar_cull,
-                                                       wave_scan=wave_scan), **kw)
+                                                       wave_scan=wave_scan, no_box_test=no_box_test,
+                                                       box_test=box_test), **kw)
     torch.cuda.synchronize()
     out = {"u": u.cpu().numpy(), "g": g.cpu().numpy(), "st": st.cpu().numpy(), "off": off}
     if ubar is not None:
@@ -517,16 +519,22 @@ def test_culling_changes_no_result_batch(B):
 
 def test_matrix_core_cull_matches_vector_cull(B):
     """The FP32 cluster test on the matrix cores (members scanned pair by
-    pair, or by every lane of the wave) and on the vector ALUs skip different
-    (always non-minimal) clusters; walks and outputs are identical, and the
-    pair-compacted scan evaluates the fewest member distances."""
+    pair, with the bounding-box test in every dimension, by dimension or
+    never, or by every lane of the wave) and on the vector ALUs skip
+    different (always non-minimal) clusters; walks and outputs are
+    identical, and the more pairs the box test sees the fewer member
+    distances are evaluated."""
     for s in _cull_scenes():
         a = gpu_estimate(B, s)
         b = gpu_estimate(B, s, scalar_cull=True)
         c = gpu_estimate(B, s, wave_scan=True)
-        for x, y, z in zip(a, b, c):
+        n = gpu_estimate(B, s, no_box_test=True)
+        f = gpu_estimate(B, s, box_test=True)
+        for x, y, z, w, v in zip(a, b, c, n, f):
             assert np.array_equal(x, y), s["name"]
             assert np.array_equal(x, z), s["name"]
+            assert np.array_equal(x, w), s["name"]
+            assert np.array_equal(x, v), s["name"]
         dom = B.Domain(s)
         for q in range(2):
             ra = B.wos_debug_walks(dom, s["queries"][q], q, 0, 128, s["sigma"], s["eps"], s["seed"],
@@ -540,14 +548,18 @@ def test_matrix_core_cull_matches_vector_cull(B):
     a = gpu_batch(B, envs, 256, 5, ubar=ubar)
     b = gpu_batch(B, envs, 256, 5, ubar=ubar, scalar_cull=True)
     c = gpu_batch(B, envs, 256, 5, ubar=ubar, wave_scan=True)
+    n = gpu_batch(B, envs, 256, 5, ubar=ubar, no_box_test=True)
+    f = gpu_batch(B, envs, 256, 5, ubar=ubar, box_test=True)
     for k in ("u", "g", "dx", "ds", "dg"):
-        assert np.array_equal(a[k], b[k]), k
-        assert np.array_equal(a[k], c[k]), k
-    assert np.array_equal(a["st"][:, :12], b["st"][:, :12])
-    assert np.array_equal(a["st"][:, :12], c["st"][:, :12])
-    ma, mb, mc = a["st"][:, 12].sum(), b["st"][:, 12].sum(), c["st"][:, 12].sum()
-    print(f"member distances per walk, pairs / wave scan / vector cull: {ma:.4g} / {mc:.4g} / {mb:.4g}")
-    assert ma <= mc and ma <= mb
+        for o in (b, c, n, f):
+            assert np.array_equal(a[k], o[k]), k
+    for o in (b, c, n, f):
+        assert np.array_equal(a["st"][:, :12], o["st"][:, :12])
+    ma, mb, mc, mn, mf = (o["st"][:, 12].sum() for o in (a, b, c, n, f))
+    print(f"member distances per walk, pairs with the box test everywhere / by dimension / never, wave scan, "
+          f"vector cull: {mf:.4g} / {ma:.4g} / {mn:.4g} / {mc:.4g} / {mb:.4g}")
+    assert mf <= ma <= mn <= mc and mn <= mb
+    assert np.all(n["st"][:, 15] == 0) and f["st"][:, 15].sum() >= a["st"][:, 15].sum() > 0
 
 
 def _dense_cloud(seed=21, boxes=False):
@@ -603,9 +615,10 @@ def test_pair_queue_overflow_is_exact(B, boxes):
     thr = np.min(np.minimum(x0 - s["outer"]["lo"], s["outer"]["hi"] - x0))
     need = np.linalg.norm(cl[:, :3] - x0, axis=1) - cl[:, 3] <= thr
     per_tile = [need[t:t + 16].sum() for t in range(0, len(need), 16)]
-    assert 64 * max(per_tile) > 320 - 63, per_tile
+    assert 64 * max(per_tile) > 256 - 63, per_tile
     a = gpu_estimate(B, s)
-    for kw in (dict(full_scan=True), dict(wave_scan=True), dict(scalar_cull=True)):
+    for kw in (dict(full_scan=True), dict(wave_scan=True), dict(scalar_cull=True), dict(no_box_test=True),
+               dict(box_test=True)):
         b = gpu_estimate(B, s, **kw)
         for x, y in zip(a, b):
             assert np.array_equal(x, y), kw
