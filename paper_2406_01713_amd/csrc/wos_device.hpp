@@ -606,8 +606,8 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v)
 
 // Min over the members of the clusters each lane may need (thr as for
 // cluster_min), with the cluster test on the matrix cores, a bounding-box
-// test of the pairs it keeps (box_test, wave-uniform), and the members of
-// the pairs that pass both scanned pair by pair.  Requires every lane of the wave to be active; lds is
+// test of the pairs it keeps (BOXT), and the members of the pairs that pass
+// both scanned pair by pair.  Requires every lane of the wave to be active; lds is
 // the wave's kPairLds-word slice (first queue, member queue, minima).  evals:
 // member distances evaluated by the wave; boxes: bounding boxes tested.
 //
@@ -617,11 +617,11 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v)
 // pairs are queued in one pass.  A tile whose pairs would overflow the queue
 // first tests the pairs already waiting, then goes two need bits at a time
 // (at most 128 pairs each).
-template <int D, bool BOX>
+template <int D, bool BOX, bool BOXT>
 __device__ __forceinline__ float cluster_min_pairs(cptr<float> rows, const float* __restrict__ mf,
-                                                   const float* __restrict__ cb, bool box_test, int n_cl,
-                                                   const float (&x)[D], float thr, bool live, uint64_t& evals,
-                                                   uint64_t& boxes, uint32_t* lds)
+                                                   const float* __restrict__ cb, int n_cl, const float (&x)[D],
+                                                   float thr, bool live, uint64_t& evals, uint64_t& boxes,
+                                                   uint32_t* lds)
 {
     const int lane = threadIdx.x & (kWave - 1);
     uint32_t* queue = lds;
@@ -641,20 +641,20 @@ __device__ __forceinline__ float cluster_min_pairs(cptr<float> rows, const float
     int mqn = 0;  // member-queue pairs (wave-uniform), < 64 between rounds
     uint32_t tested = 0, pairs = 0;
     // box-test first-queue entries [base, base + count); a full member queue
-    // evaluates its last 64.  Without the box test (box_test false,
-    // wave-uniform) the entries go straight to a member round.
+    // evaluates its last 64.  Without the box test the entries go straight to
+    // a member round.
     auto test_round = [&](int base, int count) {
-        if (!box_test) {
+        if constexpr (!BOXT) {
             pairs += (uint32_t)count;
             pair_round<D, BOX>(rows, n_cl, queue, base, count, x, best);
-            return;
-        }
-        box_round<D>(cb, n_cl, queue, base, count, x, thr, mq, mqn);
-        tested += (uint32_t)count;
-        if (mqn >= kWave) {
-            mqn -= kWave;
-            pairs += kWave;
-            pair_round<D, BOX>(rows, n_cl, mq, mqn, kWave, x, best);
+        } else {
+            box_round<D>(cb, n_cl, queue, base, count, x, thr, mq, mqn);
+            tested += (uint32_t)count;
+            if (mqn >= kWave) {
+                mqn -= kWave;
+                pairs += kWave;
+                pair_round<D, BOX>(rows, n_cl, mq, mqn, kWave, x, best);
+            }
         }
     };
     // the next tile's features load while this tile is tested and queued (the
@@ -716,15 +716,17 @@ __device__ __forceinline__ float cluster_min_pairs(cptr<float> rows, const float
     // member round, they go together without their box test (that round runs
     // anyway unless every box test fails, and a skipped test only adds member
     // distances, which never change the minimum)
-    if (!box_test) {
+    if constexpr (!BOXT) {
         if (qn > 0) test_round(0, qn);
-    } else if (qn + mqn <= kWave) {
-        if (lane < qn) mq[mqn + lane] = queue[lane];
-        mqn += qn;
     } else {
-        test_round(0, qn);
+        if (qn + mqn <= kWave) {
+            if (lane < qn) mq[mqn + lane] = queue[lane];
+            mqn += qn;
+        } else {
+            test_round(0, qn);
+        }
+        if (mqn > 0) pair_round<D, BOX>(rows, n_cl, mq, 0, mqn, x, best);
     }
-    if (mqn > 0) pair_round<D, BOX>(rows, n_cl, mq, 0, mqn, x, best);
     evals += ((uint64_t)pairs + (uint64_t)mqn) * kCluster;
     boxes += tested;
     return float_of_ord(best[lane]);
@@ -768,9 +770,14 @@ __device__ __forceinline__ T distance(cenv<T> p, const T (&x)[D], int& cls, Work
         bool done = false;
         if constexpr (sizeof(T) == 4) {
             if (p->use_mfma == 2) {
-                db = cluster_min_pairs<D, true>(to_const(p->box_cl), fresh(p)->box_mf, fresh(p)->box_cb,
-                                                fresh(p)->box_test != 0, fresh(p)->n_cl_box, xg, dga, live, eb,
-                                                cbt, wc.pairs);
+                if (p->box_test)
+                    db = cluster_min_pairs<D, true, true>(to_const(fresh(p)->box_cl), fresh(p)->box_mf,
+                                                          fresh(p)->box_cb, fresh(p)->n_cl_box, xg, dga, live, eb,
+                                                          cbt, wc.pairs);
+                else
+                    db = cluster_min_pairs<D, true, false>(to_const(fresh(p)->box_cl), fresh(p)->box_mf,
+                                                           fresh(p)->box_cb, fresh(p)->n_cl_box, xg, dga, live, eb,
+                                                           cbt, wc.pairs);
                 done = true;
             } else if (p->use_mfma) {
                 db = cluster_min_mfma<D, true>(to_const(p->box_cl), fresh(p)->box_mf, fresh(p)->n_cl_box, xg,
@@ -792,9 +799,14 @@ __device__ __forceinline__ T distance(cenv<T> p, const T (&x)[D], int& cls, Work
         bool done = false;
         if constexpr (sizeof(T) == 4) {
             if (p->use_mfma == 2) {
-                ds = cluster_min_pairs<D, false>(to_const(p->sph_cl), fresh(p)->sph_mf, fresh(p)->sph_cb,
-                                                 fresh(p)->box_test != 0, fresh(p)->n_cl_sph, xg,
-                                                 Math<T>::min(dga, db), live, es, cbt, wc.pairs);
+                if (p->box_test)
+                    ds = cluster_min_pairs<D, false, true>(to_const(fresh(p)->sph_cl), fresh(p)->sph_mf,
+                                                           fresh(p)->sph_cb, fresh(p)->n_cl_sph, xg,
+                                                           Math<T>::min(dga, db), live, es, cbt, wc.pairs);
+                else
+                    ds = cluster_min_pairs<D, false, false>(to_const(fresh(p)->sph_cl), fresh(p)->sph_mf,
+                                                            fresh(p)->sph_cb, fresh(p)->n_cl_sph, xg,
+                                                            Math<T>::min(dga, db), live, es, cbt, wc.pairs);
                 done = true;
             } else if (p->use_mfma) {
                 ds = cluster_min_mfma<D, false>(to_const(p->sph_cl), fresh(p)->sph_mf, fresh(p)->n_cl_sph, xg,
