@@ -502,17 +502,23 @@ __device__ __forceinline__ int entry_walker(uint32_t e)
     return (int)((q & 0x30u) | ((q & 3u) << 2) | ((q >> 2) & 3u));
 }
 
-// Evaluate queue entries [base, base + count), count <= 64, one per lane.
-// All lanes of the wave take part (the walker positions move by lane
-// shuffles).
+// Evaluate queue entries [base, base + count), count <= 64, one per lane; a
+// round of at most 32 (16, 8) entries gives each entry 2 (4, 8) lanes, which
+// split its members (lane sub of an entry takes members sub, sub + 2^sh, ...),
+// so a part-filled round, such as a step's last, costs a half (a quarter, an
+// eighth) of a full one.  The minimum is the same: every member is evaluated
+// once and folds into its walker's slot.  All lanes of the wave take part
+// (the walker positions move by lane shuffles).
 template <int D, bool BOX>
 __device__ __forceinline__ void pair_round(cptr<float> rows, int n_cl, const uint32_t* queue, int base, int count,
                                            const float (&x)[D], uint32_t* best)
 {
     constexpr int S = BOX ? box_stride(D) : sph_stride(D);
     const int lane = threadIdx.x & (kWave - 1);
-    const bool act = lane < count;
-    const uint32_t e = act ? queue[base + lane] : 0u;
+    const int sh = count > 32 ? 0 : count > 16 ? 1 : count > 8 ? 2 : 3;  // wave-uniform
+    const int slot = lane >> sh;
+    const bool act = slot < count;
+    const uint32_t e = act ? queue[base + slot] : 0u;
     const int w = entry_walker(e);
     int c = (int)(e >> 6);
     c = c < n_cl ? c : n_cl - 1;  // an entry never points past the table
@@ -522,11 +528,19 @@ __device__ __forceinline__ void pair_round(cptr<float> rows, int n_cl, const uin
     if (act) {
         cptr<float> r = rows + (int64_t)c * (kCluster * S);
         float m = Math<float>::inf();
-        // two members per iteration: the rows arrive in vector registers, so a
-        // full unroll would hold all eight clusters' members at once
+        if (sh == 0) {
+            // two members per iteration: the rows arrive in vector registers,
+            // so a full unroll would hold all eight clusters' members at once
 #pragma unroll 2
-        for (int j = 0; j < kCluster; ++j)
-            m = Math<float>::min(m, BOX ? box_dist<float, D>(xw, r + j * S) : sphere_dist<float, D>(xw, r + j * S));
+            for (int j = 0; j < kCluster; ++j)
+                m = Math<float>::min(m, BOX ? box_dist<float, D>(xw, r + j * S) : sphere_dist<float, D>(xw, r + j * S));
+        } else {
+            r += (lane & ((1 << sh) - 1)) * S;
+            const int n = kCluster >> sh;
+            for (int j = 0; j < n; ++j)
+                m = Math<float>::min(m, BOX ? box_dist<float, D>(xw, r + (j << sh) * S)
+                                            : sphere_dist<float, D>(xw, r + (j << sh) * S));
+        }
         atomicMin(&best[w], ord_of(m));
     }
 }
