@@ -547,9 +547,9 @@ __device__ __forceinline__ void pair_round(cptr<float> rows, int n_cl, const uin
 
 // Bounding-box test of queue entries [base, base + count), count <= 64, one
 // per lane: an entry passes unless the distance from its walker to its
-// cluster's box, times Cull<float>::shrink, exceeds max(thr, 0) of that
-// walker; passing entries are appended to the member queue mq (mqn entries,
-// fewer than 64 on entry, wave-uniform).
+// cluster's box, times Cull<float>::shrink, exceeds thr0 = max(thr, 0) of
+// that walker; passing entries are appended to the member queue mq (mqn
+// entries, fewer than 64 on entry, wave-uniform).
 //
 // Soundness (FP32, unit roundoff u = 2^-24): the stored box contains the
 // members' box enlarged by delta = 2^-16 times its diagonal in every
@@ -564,7 +564,7 @@ __device__ __forceinline__ void pair_round(cptr<float> rows, int n_cl, const uin
 // gives distance 0 or NaN and passes.
 template <int D>
 __device__ __forceinline__ void box_round(const float* __restrict__ cb, int n_cl, const uint32_t* queue, int base,
-                                          int count, const float (&x)[D], float thr, uint32_t* mq, int& mqn)
+                                          int count, const float (&x)[D], float thr0, uint32_t* mq, int& mqn)
 {
     const int lane = threadIdx.x & (kWave - 1);
     const bool act = lane < count;
@@ -575,7 +575,7 @@ __device__ __forceinline__ void box_round(const float* __restrict__ cb, int n_cl
     float xw[D];
 #pragma unroll
     for (int i = 0; i < D; ++i) xw[i] = __shfl(x[i], w, kWave);
-    const float tw = __builtin_fmaxf(__shfl(thr, w, kWave), 0.0f);
+    const float tw = __shfl(thr0, w, kWave);
     const mf4* r = reinterpret_cast<const mf4*>(cb + (int64_t)c * kClusterBox);
     const mf4 lo0 = r[0], hi0 = r[2];
     mf4 lo1 = lo0, hi1 = hi0;
@@ -592,7 +592,7 @@ __device__ __forceinline__ void box_round(const float* __restrict__ cb, int n_cl
         acc = __builtin_fmaf(t, t, acc);
     }
     const bool pass = act && !(__builtin_amdgcn_sqrtf(acc) * Cull<float>::shrink > tw);
-    const uint64_t m = __ballot(pass);
+    const uint64_t m = __builtin_amdgcn_ballot_w64(pass);
     if (pass) {
         const uint32_t rank =
             __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
@@ -651,6 +651,7 @@ __device__ __forceinline__ float cluster_min_pairs(cptr<float> rows, const float
     // q = (bit << 2) | g = 16 rt + 4 r + g, so each entry is one shift-or of
     // the bit index into the lane's constant part
     const uint32_t lane_e = ((uint32_t)(lane & (kMfmaTile - 1)) << 6) | (uint32_t)(lane >> 4);
+    const float thr0 = __builtin_fmaxf(thr, 0.0f);  // the box test's threshold
     int qn = 0;   // first-queue pairs (wave-uniform), < 64 between tiles
     int mqn = 0;  // member-queue pairs (wave-uniform), < 64 between rounds
     uint32_t tested = 0, pairs = 0;
@@ -662,7 +663,7 @@ __device__ __forceinline__ float cluster_min_pairs(cptr<float> rows, const float
             pairs += (uint32_t)count;
             pair_round<D, BOX>(rows, n_cl, queue, base, count, x, best);
         } else {
-            box_round<D>(cb, n_cl, queue, base, count, x, thr, mq, mqn);
+            box_round<D>(cb, n_cl, queue, base, count, x, thr0, mq, mqn);
             tested += (uint32_t)count;
             if (mqn >= kWave) {
                 mqn -= kWave;

@@ -392,7 +392,7 @@ __device__ __forceinline__ void run_unit(cenv<float> p, CBatch& be, int64_t loca
             }
         }
         // lane refill: finished lanes take the unit's next walks in lane order
-        const uint64_t m = __ballot(fin);
+        const uint64_t m = __builtin_amdgcn_ballot_w64(fin);
         if (m) {
             if (fin) {
                 const uint32_t rank =
