@@ -158,7 +158,7 @@ plain_kernel(const EnvP<T>* penv, const T* __restrict__ queries, int64_t n_units
     // every lane steps until the wave's last walk ends (a finished lane runs
     // along idle), so the obstacle scans and the work tally stay wave-uniform
     bool done = !active;
-    while (__any(!done)) {
+    while (__builtin_amdgcn_ballot_w64(!done) != 0) {
         WalkEnd<T> ek;
         const bool fin = walker_step<T, D, BWD, D, SRC>(p, s, q_base + (uint32_t)q, k0, k1, ek, wc, !done);
         if (fin && !done) {
@@ -333,6 +333,10 @@ __device__ __forceinline__ void run_unit(cenv<float> p, CBatch& be, int64_t loca
     const int64_t sp = local - ql * be.splits;
     const int64_t w_begin = sp * (int64_t)be.wps;
     const int64_t w_end = (w_begin + be.wps < n_walks) ? w_begin + be.wps : n_walks;
+    // walks of the unit counted from w_begin in 32 bits (a unit holds at
+    // most wps < 2^31 walks); walk ids are taken modulo 2^32 as before
+    const int32_t n_unit = (int32_t)(w_end - w_begin);
+    const uint32_t id0 = (uint32_t)w_begin;
 
     float xq[kMaxDim];
     cptr<float> qrow = to_const(queries) + (be.q_off + ql) * be.q_stride;
@@ -355,14 +359,13 @@ __device__ __forceinline__ void run_unit(cenv<float> p, CBatch& be, int64_t loca
     // walker) only take part in the member scans of the pair rounds
     const int lanes = be.lanes;
     Walker<float, kMaxDim> s;
-    int64_t next = w_begin + lane;
-    bool active = lane < lanes && next < w_end;
-    walker_start<float, kMaxDim, kMaxDim>(s, xq, (uint32_t)next);
-    int64_t base = w_begin + lanes;
+    bool active = lane < lanes && lane < n_unit;
+    walker_start<float, kMaxDim, kMaxDim>(s, xq, id0 + (uint32_t)lane);
+    int32_t base = lanes;
     const uint32_t qi = (uint32_t)ql;
     WorkCount wc(pairs);
 
-    while (__any(active)) {
+    while (__builtin_amdgcn_ballot_w64(active) != 0) {
         WalkEnd<float> e;
         // idle lanes (the unit has no walks left for them) step along
         bool fin = step_any_d<BWD, SRC>(d, p, s, qi, k0, k1, e, wc, active);
@@ -397,9 +400,9 @@ __device__ __forceinline__ void run_unit(cenv<float> p, CBatch& be, int64_t loca
             if (fin) {
                 const uint32_t rank =
                     __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-                const int64_t wn = base + rank;
-                if (wn < w_end) {
-                    walker_start<float, kMaxDim, kMaxDim>(s, xq, (uint32_t)wn);
+                const int32_t wn = base + (int32_t)rank;
+                if (wn < n_unit) {
+                    walker_start<float, kMaxDim, kMaxDim>(s, xq, id0 + (uint32_t)wn);
                 } else {
                     active = false;
                 }
