@@ -600,13 +600,14 @@ def _dense_cloud(seed=21, boxes=False):
 @pytest.mark.parametrize("boxes", [False, True])
 def test_pair_queue_overflow_is_exact(B, boxes):
     """A tile whose (walker, cluster) pairs overflow the per-wave queue is
-    queued row tile by row tile after the waiting pairs are evaluated: walks
+    queued two need bits at a time after the waiting pairs are tested: walks
     and outputs stay bitwise those of the wave-uniform, vector-ALU and full
-    scans, in the plain, debug-walk and batched launches (sphere and box
+    scans, and of the pair scan with the bounding-box test forced on or off,
+    in the plain, debug-walk and batched launches (sphere and box
     obstacles)."""
     s = _dense_cloud(boxes=boxes)
     # precondition: at step 0 the 64 walkers of query 0 need more than
-    # 320 - 63 pairs in some tile (they all sit at the query point)
+    # 256 - 63 pairs in some tile (they all sit at the query point)
     if boxes:
         cl = B.wos_debug_clusters(3, box_c=s["box_c"], box_h=s["box_h"])["box"][1]
     else:
