@@ -512,10 +512,10 @@ def test_culling_changes_no_result_batch(B):
             assert np.all(a["st"][sl, 15] <= -(-M // 8) * steps * (1 + 1e-12))
             # the box test runs by default where the obstacles depend on 6 or
             # more coordinates
-            if s["d"] >= 6:
-                assert np.any(a["st"][sl, 15] > 0), e
-            else:
+            if s["d"] < 6:
                 assert np.all(a["st"][sl, 15] == 0), e
+            elif M >= 128:
+                assert np.any(a["st"][sl, 15] > 0), e
             saved += (b["st"][sl, 12] - a["st"][sl, 12]).sum()
             done += (a["st"][sl, 12] + a["st"][sl, 14]).sum()
             full += b["st"][sl, 12].sum()
