@@ -153,3 +153,19 @@ def test_rr_paths_reach_the_goal_and_screening_shortens_them(B):
             res[distance, sigma] = L
     for distance in ("ik", "lipschitz"):
         assert res[distance, 5.0] < res[distance, 0.0], res
+
+
+def test_rr_ik_points_culling_is_exact(B):
+    """The RR task's 200 IK points (radius-0 obstacles, clustered): the
+    culled scan, with the pair scan's bounding-box test by default (off in
+    two dimensions), forced on, or forced off, gives bitwise the walks of a
+    full scan."""
+    s = S.scene_rr("ik", sigma=5.0, n_walks=2048)
+    rng = np.random.default_rng(3)
+    q = np.concatenate([np.asarray(s["queries"]),
+                        rng.uniform([-np.pi / 2 + 0.2, -np.pi + 0.2], [3 * np.pi / 2 - 0.2, np.pi - 0.2], size=(7, 2))])
+    a = gpu_estimate(B, s, queries=q)
+    for kw in (dict(full_scan=True), dict(box_test=True), dict(no_box_test=True)):
+        b = gpu_estimate(B, s, queries=q, **kw)
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y), kw

@@ -131,17 +131,22 @@ def test_extruded_annulus_closed_form(B, d, sigma):
 @pytest.mark.parametrize("fp64", [False, True])
 def test_extruded_clusters(B, oracle, fp64):
     """160 extruded cylinders (clustered): culled scans give bitwise the walks
-    of a full scan, the matrix-core and vector cluster tests agree (FP32),
-    and the walks follow the oracle's."""
+    of a full scan, the matrix-core and vector cluster tests and the pair
+    scan with the bounding-box test forced on agree (FP32), and the walks
+    follow the oracle's."""
     s = _cylinders(4)
     a = gpu_estimate(B, s, fp64=fp64)
     b = gpu_estimate(B, s, fp64=fp64, full_scan=True)
     for x, y in zip(a, b):
         assert np.array_equal(x, y)
     if not fp64:
-        c = gpu_estimate(B, s, scalar_cull=True)
-        for x, y in zip(a, c):
-            assert np.array_equal(x, y)
+        # vector cluster test; the pair scan's bounding-box test forced on
+        # (off by default for obstacles of 2 coordinates: the boxes' free
+        # coordinates then span only the members' radii around 0)
+        for kw in (dict(scalar_cull=True), dict(box_test=True)):
+            c = gpu_estimate(B, s, **kw)
+            for x, y in zip(a, c):
+                assert np.array_equal(x, y), kw
     dom = B.Domain(s)
     odom = oracle.Domain(s)
     tol = 1e-9 if fp64 else 2e-4
