@@ -479,6 +479,8 @@ int wos_debug_clusters(int d, const wos_spheres* spheres, const wos_boxes* boxes
  * wos_debug_cluster_boxes -- host only, no device: the bounding boxes that
  * the FP32 kernels test the (walker, cluster) pairs kept by the cluster
  * bound against, one per cluster of wos_debug_clusters (same cluster order).
+ * Like the clusters, they only speed up the distance to the boundary that
+ * every walk step queries (Sec. IV-A); the paper has no such structure.
  *   spheres, boxes   as wos_create_domain (either may be NULL)
  *   out_n_cl         host int64[2]: sphere clusters, box clusters
  *   box_sph          host double, capacity n_cl_sph * 2 d (may be NULL): per
