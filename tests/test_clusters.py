@@ -205,8 +205,9 @@ def test_box_test_is_sound_in_fp32(B):
     """Wherever the FP32 bounding-box value of a cluster is positive, every
     member's FP32 distance is at least that value, so a pair skipped because
     the value exceeds max(thr, 0) has no member at or below thr.  Probes lie
-    on, just off and inside members, just outside the faces and corners of
-    the cluster boxes, and uniformly in the outer box."""
+    on, just off and inside members, just past members' extreme points along
+    the axes (where a member touches its cluster's box), just outside the
+    faces and corners of the cluster boxes, and uniformly in the outer box."""
     rng = np.random.default_rng(12)
     for name, s in _sets() + _far_tight_sets():
         d = s["d"]
@@ -229,7 +230,14 @@ def test_box_test_is_sound_in_fp32(B):
             face[np.arange(800), ax] = corner[np.arange(800), ax]
             off = rng.choice([0.0, 1e-7, 1e-5, 1e-3], size=(800, 1))
             push = np.where(side, 1.0, -1.0) * off
-            x = np.concatenate([x, corner + push, face + push]).astype(np.float32)
+            # just past a member's extreme point along an axis, where its
+            # surface touches its cluster's box face: the tightest case
+            j = rng.integers(0, len(c), 800)
+            ax = rng.integers(0, d, 800)
+            sg = rng.choice([-1.0, 1.0], 800)
+            tip = c[j].astype(np.float64)
+            tip[np.arange(800), ax] += sg * (ext[j, ax] + rng.choice([0.0, 1e-7, 1e-5, 1e-3], 800))
+            x = np.concatenate([x, corner + push, face + push, tip]).astype(np.float32)
             dist = _sphere_d32(x, c, r_or_h) if kind == "sph" else _box_d32(x, c, r_or_h)
             lb = _box_lb32(x, lohi, d)
             worst = np.inf
