@@ -312,6 +312,18 @@ def test_debug_clusters_rejects_bad_input(B):
         B.wos_debug_clusters(3, np.zeros((70, 3)), -np.ones(70))
 
 
+def test_debug_cluster_boxes_rejects_bad_input(B):
+    import ctypes as C
+    n = (C.c_int64 * 2)()
+    assert B.lib.wos_debug_cluster_boxes(1, None, None, n, None, None) == B.WOS_EDIM
+    assert B.lib.wos_debug_cluster_boxes(3, None, None, None, None, None) == B.WOS_EINVAL
+    with pytest.raises(B.WosError):
+        B.wos_debug_cluster_boxes(3, np.zeros((70, 3)), -np.ones(70))
+    # no obstacles, or fewer than 64: no clusters, no boxes
+    out = B.wos_debug_cluster_boxes(3, np.zeros((10, 3)), np.ones(10))
+    assert out["sph"].shape == (0, 6) and out["box"].shape == (0, 6)
+
+
 def _mfma_features(x, thr, bc, br, d):
     """Walker features (FP32, as the kernel forms them) and cluster features
     (FP64 rounded once to FP32, as the host forms them) of the matrix-core
