@@ -460,7 +460,7 @@ def test_batch_matches_plain_per_env(B):
 
 def _cull_scenes():
     big = S.scene_c4_env(5, n_walks=256, seed=2, q_cap=6)
-    return [subset("c3", 8, 256, seed=2), subset("c5", 6, 256, seed=2), big]
+    return [subset("c3", 8, 256, seed=2), subset("c5", 6, 256, seed=2), big, subset("d8", 6, 256, seed=2)]
 
 
 @pytest.mark.parametrize("fp64", [False, True])
