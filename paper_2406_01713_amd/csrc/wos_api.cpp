@@ -87,6 +87,7 @@ struct wos_domain {
     double g_goal = 1, g_obs = 0, g_outer = 0, b = 0;
     double ak[kMaxDim] = {0};
     double r_max = 0;  // largest possible empty-ball radius (bounds sigma R^2 / 4)
+    double coord_scale = 0;  // largest coordinate magnitude (plus radius) of the geometry
     // clustered copies of the obstacle tables (see EnvP): one buffer per
     // precision, [sphere rows | sphere bounds | box rows | box bounds]
     int32_t n_cl_sph = 0, n_cl_box = 0;
@@ -215,6 +216,12 @@ int make_env(const wos_domain* D, double sigma, double eps, uint64_t seed, uint3
     p.b = (T)D->b;
     p.sigma = (T)sigma;
     p.eps = (T)eps;
+    // margin of the step-to-step bound R_next <= 2 R: 2^-14 of the geometry's
+    // size exceeds the rounding of the positions and of every component's
+    // distance (a few units of 2^-24 of that size in FP32) many times over;
+    // unbounded (extruded) coordinates let |x| grow without limit, so there
+    // the bound is off
+    p.rb_abs = D->geom_d == D->d ? (T)(0x1p-14 * (1.0 + D->coord_scale)) : std::numeric_limits<T>::infinity();
     p.qsigma = (T)std::ldexp(0.25 * sigma, -m);
     for (int i = 0; i < kMaxTerms; ++i) {
         p.cC[i] = (T)(i < nC ? std::ldexp(cC[i], m * i) : 0.0);
@@ -1261,6 +1268,28 @@ int wos_create_domain(int d, const wos_spheres* spheres, const wos_boxes* boxes,
     std::vector<float> sf, bf;
     std::vector<double> sd, bd;
     obstacle_rows(d, spheres, boxes, sf, sd, bf, bd);
+    {
+        // size of the geometry: every coordinate magnitude plus radius
+        double sc = 0.0;
+        if (D->has_goal)
+            for (int i = 0; i < d; ++i) sc = std::max(sc, std::fabs(D->goal_c[i]) + D->goal_r);
+        if (D->outer_kind == WOS_OUTER_BOX)
+            for (int i = 0; i < gd; ++i) sc = std::max(sc, std::max(std::fabs(D->lo[i]), std::fabs(D->hi[i])));
+        else
+            for (int i = 0; i < gd; ++i) sc = std::max(sc, std::fabs(D->oc[i]) + D->orad);
+        for (int64_t j = 0; j < ns; ++j)
+            for (int i = 0; i < d; ++i) sc = std::max(sc, std::fabs(spheres->centers[j * d + i]) + spheres->radii[j]);
+        for (int64_t j = 0; j < nb; ++j)
+            for (int i = 0; i < d; ++i)
+                sc = std::max(sc, std::fabs(boxes->centers[j * d + i]) + boxes->half_widths[j * d + i]);
+        if (D->n_arm > 0) {
+            double reach = 0.0;
+            for (int i = 0; i < d; ++i) reach += std::fabs(D->arm_l[i]);
+            sc = std::max(sc, reach);
+            for (int64_t j = 0; j < 2 * (int64_t)D->n_arm; ++j) sc = std::max(sc, std::fabs(arm->points[j]));
+        }
+        D->coord_scale = sc;
+    }
     hipError_t e = hipGetDevice(&D->device);
     if (e == hipSuccess) e = hipMalloc(&D->sph_f, sf.size() * sizeof(float));
     if (e == hipSuccess) e = hipMalloc(&D->sph_d, sd.size() * sizeof(double));

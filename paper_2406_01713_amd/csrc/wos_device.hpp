@@ -749,10 +749,14 @@ __device__ __forceinline__ float cluster_min_pairs(cptr<float> rows, const float
 
 // R = distance to the boundary; cls = first component attaining it in the
 // order goal, spheres, boxes, outer.  The goal and outer distances come first
-// and bound the box scan, whose result then bounds the sphere scan; culled
-// clusters leave R and cls as a scan of every obstacle gives them.
+// and bound the box scan, whose result then bounds the sphere scan; ub, any
+// value at or above the R a scan of every obstacle computes (the walker's
+// bound from its previous step, +inf when it has none), bounds both scans as
+// well.  Culled clusters leave R and cls as a scan of every obstacle gives
+// them.
 template <typename T, int D>
-__device__ __forceinline__ T distance(cenv<T> p, const T (&x)[D], int& cls, WorkCount& wc, bool live)
+__device__ __forceinline__ T distance(cenv<T> p, const T (&x)[D], int& cls, WorkCount& wc, bool live,
+                                      T ub = Math<T>::inf())
 {
     T dg = Math<T>::inf();
     if (p->has_goal) {
@@ -775,6 +779,7 @@ __device__ __forceinline__ T distance(cenv<T> p, const T (&x)[D], int& cls, Work
     // the arm bound (joint coordinates, never extruded) tightens the scans
     const T da = p->n_arm ? arm_dist<T, D>(p, x) : Math<T>::inf();
     const T dga = Math<T>::min(dg, Math<T>::min(da, dout));
+    const T tg = Math<T>::min(dga, ub);  // the scans' threshold before the box result
     p = fresh(p);
     T db;
     uint32_t nb, ns;         // member distances per lane (wave-uniform scans)
@@ -787,22 +792,22 @@ __device__ __forceinline__ T distance(cenv<T> p, const T (&x)[D], int& cls, Work
             if (p->use_mfma == 2) {
                 if (p->box_test)
                     db = cluster_min_pairs<D, true, true>(to_const(fresh(p)->box_cl), fresh(p)->box_mf,
-                                                          fresh(p)->box_cb, fresh(p)->n_cl_box, xg, dga, live, eb,
+                                                          fresh(p)->box_cb, fresh(p)->n_cl_box, xg, tg, live, eb,
                                                           cbt, wc.pairs);
                 else
                     db = cluster_min_pairs<D, true, false>(to_const(fresh(p)->box_cl), fresh(p)->box_mf,
-                                                           fresh(p)->box_cb, fresh(p)->n_cl_box, xg, dga, live, eb,
+                                                           fresh(p)->box_cb, fresh(p)->n_cl_box, xg, tg, live, eb,
                                                            cbt, wc.pairs);
                 done = true;
             } else if (p->use_mfma) {
                 db = cluster_min_mfma<D, true>(to_const(p->box_cl), fresh(p)->box_mf, fresh(p)->n_cl_box, xg,
-                                               dga, live, nb);
+                                               tg, live, nb);
                 done = true;
             }
         }
         if (!done)
             db = cluster_min<T, D, true>(to_const(fresh(p)->box_cl), to_const(fresh(p)->box_bnd), fresh(p)->n_cl_box, xg,
-                                         dga, live, nb);
+                                         tg, live, nb);
     } else {
         db = boxes_min<T, D>(to_const(p->box), fresh(p)->n_box, xg);
         nb = (uint32_t)fresh(p)->n_box;
@@ -817,21 +822,21 @@ __device__ __forceinline__ T distance(cenv<T> p, const T (&x)[D], int& cls, Work
                 if (p->box_test)
                     ds = cluster_min_pairs<D, false, true>(to_const(fresh(p)->sph_cl), fresh(p)->sph_mf,
                                                            fresh(p)->sph_cb, fresh(p)->n_cl_sph, xg,
-                                                           Math<T>::min(dga, db), live, es, cbt, wc.pairs);
+                                                           Math<T>::min(tg, db), live, es, cbt, wc.pairs);
                 else
                     ds = cluster_min_pairs<D, false, false>(to_const(fresh(p)->sph_cl), fresh(p)->sph_mf,
                                                             fresh(p)->sph_cb, fresh(p)->n_cl_sph, xg,
-                                                            Math<T>::min(dga, db), live, es, cbt, wc.pairs);
+                                                            Math<T>::min(tg, db), live, es, cbt, wc.pairs);
                 done = true;
             } else if (p->use_mfma) {
                 ds = cluster_min_mfma<D, false>(to_const(p->sph_cl), fresh(p)->sph_mf, fresh(p)->n_cl_sph, xg,
-                                                Math<T>::min(dga, db), live, ns);
+                                                Math<T>::min(tg, db), live, ns);
                 done = true;
             }
         }
         if (!done)
             ds = cluster_min<T, D, false>(to_const(fresh(p)->sph_cl), to_const(fresh(p)->sph_bnd), fresh(p)->n_cl_sph,
-                                          xg, Math<T>::min(dga, db), live, ns);
+                                          xg, Math<T>::min(tg, db), live, ns);
     } else {
         ds = spheres_min<T, D>(to_const(p->sph), fresh(p)->n_sph, xg);
         ns = (uint32_t)fresh(p)->n_sph;
@@ -1107,6 +1112,7 @@ struct Walker {
     uint32_t k;
     uint32_t w;
     int32_t ex;  // W, W1, src, src1 and srcS hold their values times 2^-ex (FP32 only)
+    T rb;        // bound on this step's R from the previous one (+inf on a walk's first step)
 };
 
 template <typename T>
@@ -1141,6 +1147,7 @@ __device__ __forceinline__ void walker_start(Walker<T, DA>& s, const T (&xq)[DA]
     s.k = 0;
     s.w = w;
     s.ex = 0;
+    s.rb = Math<T>::inf();
 }
 
 // FP32 walks: the weight product of a long walk at a large screening
@@ -1186,8 +1193,16 @@ __device__ __forceinline__ bool walker_step(cenv<T> p0, Walker<T, DA>& s, uint32
     static_assert(DA >= D, "walker storage narrower than the dimension");
     const T(&x)[D] = reinterpret_cast<const T(&)[D]>(s.x);
     int cls;
-    const T R = distance<T, D>(fresh(p0), x, cls, wc, live);
+    // the step-to-step bound, in the dimensions where it culls (kStepBoundMaxDim)
+    constexpr bool kBound = D <= kStepBoundMaxDim;
+    const T R = distance<T, D>(fresh(p0), x, cls, wc, live, kBound ? s.rb : Math<T>::inf());
     cenv<T> p = fresh(p0);
+    // R(x) is a minimum of distances, each 1-Lipschitz, and the walker moves
+    // R: the next R is at most 2 R, and with the margins (rb_abs covers the
+    // rounding of the positions and of every component's computed distance,
+    // +inf where coordinates are unbounded) at most this computed bound, so
+    // it is a threshold the scans may cull against without changing R or cls
+    if (kBound) s.rb = Math<T>::fma(R, T(2.001953125), p->rb_abs);  // 2 (1 + 2^-10)
     const uint32_t k = s.k;
     if (R < p->eps) {
         const T g = boundary_value<T, D>(p, x, cls);

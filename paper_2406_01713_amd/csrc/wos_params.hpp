@@ -64,6 +64,15 @@ constexpr int kPairLds = kPairCap + kBoxQueue + kWave;
 // nearly as tight as its box, and the test costs more than it saves.
 constexpr int kBoxTestMinDim = 6;
 
+// A walker's R at one step is at most twice its R at the step before (R is a
+// minimum of 1-Lipschitz distances and the walker moves R), so that bound,
+// with rounding margins, also thresholds the obstacle scans.  It pays where
+// obstacles, not the outer box, are usually nearest: dense scenes in few
+// dimensions (2-4x fewer clusters kept at d = 3-4, 1.3-1.5x at d = 5, under
+// 5 % at d = 6-7, CPU walk simulation of the ragged batch); above
+// kStepBoundMaxDim the kernels are built without it.
+constexpr int kStepBoundMaxDim = 5;
+
 // Cluster bounding boxes (FP32 kernels): per cluster lo[kMaxDim] then
 // hi[kMaxDim] (zero past d), the box of the members enlarged by a margin
 // (see build_cluster_boxes) and rounded outwards.
@@ -109,6 +118,7 @@ struct EnvP {
     T g_goal, g_obs, g_outer, b;
     T ak[kMaxDim];
     T sigma, eps, qsigma;      // qsigma = 2^-m sigma / 4 (m: the series scale)
+    T rb_abs;                  // absolute margin of the step-to-step bound on R (+inf: no bound)
     T cC[kMaxTerms];           // 2^(m k) c_k, c_k = 1 / ((d/2)_k k!)
     T cC1[kMaxTerms];          // 2^(m k) c_k, c_k = 1 / ((d/2 + 1)_k k!)
     // point source amp delta_z (has_src 0: none)
