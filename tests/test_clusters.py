@@ -430,3 +430,40 @@ def test_matrix_core_cull_test_is_sound_in_fp32(B, order):
                 assert not bad.any(), (name, kind, rel, np.argwhere(bad)[:3])
                 checked += skip.sum()
             assert checked > 0
+
+
+def test_step_bound_holds_in_fp32():
+    """The walkers' step-to-step bound: R at a step is at most twice R at
+    the step before (a minimum of 1-Lipschitz distances; the walker moves
+    R), and the FP32 walk stays within the kernels' margins, 2 R (1 + 2^-10)
+    + 2^-14 (1 + size of the geometry).  Walks emulated in FP32 (positions
+    updated by a rounded multiply-add, distances as the kernels form them) in
+    dense 3- and 4-D sphere scenes and a 7-D one, where the ratio comes
+    closest to 2 (steps towards a near obstacle)."""
+    rng = np.random.default_rng(21)
+    worst = -np.inf
+    for e in (105, 1, 61, 7):
+        s = S.scene_c4_env(e, n_walks=16, q_cap=64)
+        d = s["d"]
+        c = np.asarray(s["sph_c"], np.float32)
+        r = np.asarray(s["sph_r"], np.float32)
+        lo, hi = np.float32(-np.pi), np.float32(np.pi)
+        scale = max(np.abs(c).max() + r.max(), np.pi, np.abs(s["goal_c"]).max() + s["goal_r"])
+        x = np.asarray(s["queries"], np.float32)[:64].copy()
+        Rp = None
+        for _ in range(60):
+            dout = np.minimum(x - lo, hi - x).min(1).astype(np.float32)
+            gc = np.asarray(s["goal_c"], np.float32)
+            dg = (np.sqrt(_f32_sqdist(x, gc[None])[:, 0]).astype(np.float32) - np.float32(s["goal_r"])).astype(np.float32)
+            R = np.minimum(np.minimum(dout, dg), _sphere_d32(x, c, r).min(1)).astype(np.float32)
+            if Rp is not None:
+                ok = Rp > 0
+                bound = (Rp[ok].astype(np.float64) * 2.001953125 + 2.0 ** -14 * (1.0 + scale))
+                assert np.all(R[ok] <= bound), (e, np.max(R[ok] - bound))
+                worst = max(worst, float(np.max(R[ok] / np.maximum(Rp[ok], 1e-30))))
+            v = rng.normal(size=x.shape).astype(np.float32)
+            v = (v / np.sqrt((v.astype(np.float64) ** 2).sum(1, keepdims=True))).astype(np.float32)
+            Rc = np.maximum(R, np.float32(0))
+            x = (Rc[:, None].astype(np.float64) * v + x).astype(np.float32)   # fma
+            Rp = Rc
+    assert worst > 1.5   # the bound is approached
